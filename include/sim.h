@@ -1,0 +1,222 @@
+/*
+ * mmhines — C ABI of the MI355X multi-morphology compartmental simulator.
+ *
+ * The library advances a network of branched neurons through time. Each step
+ * it performs, per neuron and on the GPU (gfx950):
+ *   1. synaptic delivery: a synapse whose presynaptic neuron spiked exactly
+ *      `delay_steps` steps earlier adds its weight to its conductance
+ *      (the paper's two-level stepping, Section 2: spikes travel with a
+ *      network delay and are exchanged once per global step);
+ *   2. Hodgkin-Huxley gating and membrane current per compartment (the
+ *      current I of the cable equation, Eq. 1);
+ *   3. assembly of the per-compartment system of Eq. 2 and its right-hand
+ *      side on the neuron's parent vector p;
+ *   4. the Hines elimination and back-substitution (Algorithm 1);
+ *   5. spike detection by threshold crossing (Section 2, after Algorithm 1).
+ * Neurons are independent inside an epoch of E <= min(delay) steps, so one
+ * kernel launch advances every neuron by a whole epoch; the spike history is
+ * exchanged through device memory between epochs.
+ *
+ * Conventions for every call:
+ *  - return 0 on success or a negative SIM_E* code; sim_last_error() then
+ *    describes the failure in a library-owned string;
+ *  - input arrays are borrowed for the duration of the call and copied;
+ *  - output buffers are caller-allocated host memory with an explicit
+ *    capacity `cap` in elements;
+ *  - neuron ids and compartment order are always the caller's input order,
+ *    never the library's internal (packed) order;
+ *  - calls on one sim_t are not thread-safe; distinct sim_t are independent;
+ *  - results (voltages, spikes) are bitwise independent of the packing mode,
+ *    the autotuner and the cost model.
+ */
+#ifndef MMHINES_SIM_H
+#define MMHINES_SIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_OK 0
+#define SIM_EINVAL (-1)  /* bad argument, topology or size */
+#define SIM_ENOMEM (-2)  /* host or device allocation failed / size cap */
+#define SIM_EDEVICE (-3) /* HIP runtime error or no usable gfx950 device */
+#define SIM_ESTATE (-4)  /* call made in the wrong state */
+
+#define SIM_FP64 0          /* gates, rates and currents in double */
+#define SIM_FP32_GATING 1   /* gates, rates, currents, synaptic g in float;
+                               voltage, assembly and Hines solve in double */
+
+#define SIM_PACK_PLAIN 0    /* neurons in input order, one workgroup per pack,
+                               hardware dispatch order */
+#define SIM_PACK_COUNT 1    /* cost = compartment count; sort + LPT */
+#define SIM_PACK_LEARNED 2  /* cost = MLP prediction (falls back to COUNT
+                               when no model is given) */
+
+#define SIM_SCHED_AUTO 0       /* chosen by the autotuner, else PERSISTENT */
+#define SIM_SCHED_PERSISTENT 1 /* one resident workgroup per slot; static LPT
+                                  lists of packs */
+#define SIM_SCHED_DISPATCH 2   /* one workgroup per pack in cost order */
+
+typedef struct sim sim_t; /* opaque, owned by the library */
+
+/* Morphologies in compressed-row form (the paper's parent vector p per
+ * neuron, "Hines matrix" paragraph of Section 2). For neuron j its
+ * compartments are comp_offset[j] .. comp_offset[j+1]-1. */
+typedef struct {
+    int32_t n_neurons;           /* >= 1 */
+    const int64_t *comp_offset;  /* [n_neurons+1], comp_offset[0] = 0, strictly
+                                    increasing; at most 32767 compartments per
+                                    neuron */
+    const int32_t *parent;       /* [total] neuron-local parent index:
+                                    parent[first] = -1, 0 <= parent[i] < i */
+    const double *length_um;     /* [total] > 0, finite */
+    const double *diam_um;       /* [total] > 0, finite */
+    const uint8_t *mech;         /* [total] 0 passive leak, 1 Hodgkin-Huxley */
+    const int32_t *detector;     /* [n_neurons] local compartment watched for
+                                    spikes */
+    const double *i_ext_nA;      /* [n_neurons] constant current into the
+                                    neuron's compartment 0 */
+} sim_morphology_t;
+
+/* Membrane and channel constants (densities in S/cm^2, potentials in mV). */
+typedef struct {
+    double cm_uF_cm2, ra_ohm_cm;
+    double gnabar, gkbar, gl, ena, ek, el; /* Hodgkin-Huxley compartments */
+    double g_pas, e_pas;                   /* passive compartments */
+} sim_channels_t;
+
+/* Conductance-based exponential synapses, one record per synapse; the
+ * record index is the synapse id used for the order of simultaneous events
+ * (ascending id). */
+typedef struct {
+    int64_t n;
+    const int32_t *pre;          /* [n] presynaptic neuron */
+    const int32_t *post;         /* [n] postsynaptic neuron */
+    const int32_t *post_comp;    /* [n] local compartment of `post` */
+    const int32_t *delay_steps;  /* [n] >= 1 */
+    const double *weight_uS;     /* [n] >= 0, finite */
+} sim_synapses_t;
+
+typedef struct {
+    double dt_ms;        /* > 0 */
+    double theta;        /* axial time weighting: 0.5 (Crank-Nicolson, the
+                            factor 2 of Eq. 2) or 1.0 (backward Euler) */
+    double tau_syn_ms;   /* > 0 */
+    double e_syn_mV;
+    double v_thresh_mV;  /* spike when V crosses it upward at the detector */
+    double v_init_mV;    /* initial voltage; gates start at steady state */
+    int32_t precision;   /* SIM_FP64 | SIM_FP32_GATING */
+    int32_t packing;     /* SIM_PACK_* */
+    int32_t sched;       /* SIM_SCHED_* */
+    int32_t epoch_steps; /* 0: min(delay) capped at 64; else 1..min(delay),
+                            <= 64 */
+    int32_t autotune;    /* 1: time trial epochs over launch variants at
+                            create and keep the fastest */
+    int32_t threads;     /* workgroup size 64..1024 (multiple of 64), 0 = 256 */
+    int32_t pack_comps;  /* target compartments per pack, 0 = 1024 */
+    int32_t lds_comps;   /* largest pack kept in LDS; larger packs use global
+                            scratch. 0 = derived from the LDS budget */
+    int32_t use_graph;   /* 1: replay whole epochs from a captured hipGraph */
+    int32_t record_timings; /* 1: per-pack wall-clock time in the kernel */
+    const float *cost_model;   /* MLP parameters (sim_mlp_nparams floats) for
+                                  SIM_PACK_LEARNED, or NULL */
+    void *hip_stream;    /* hipStream_t to launch on; NULL = the library's
+                            own stream */
+} sim_params_t;
+
+typedef struct {
+    int32_t neuron; /* input order */
+    int32_t step;   /* spike happened during the transition step-1 -> step */
+} sim_spike_t;
+
+/* Fill *p with defaults (FP32 gating, COUNT packing, autotune off). */
+void sim_default_params(sim_params_t *p);
+
+/* Validate the network, lay it out on the device, compute the time-invariant
+ * coefficients on the GPU and initialise the state (V = v_init, gates at
+ * steady state, conductances 0). Every validation failure is reported before
+ * any device allocation. On success *out owns the simulation. */
+int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
+               const sim_channels_t *channels, const sim_synapses_t *syn,
+               sim_t **out);
+
+/* Advance by n_steps (>= 0) time steps; returns when the work is complete
+ * on the device. */
+int sim_step(sim_t *sim, int64_t n_steps);
+
+/* Steps simulated so far. */
+int64_t sim_time_steps(const sim_t *sim);
+
+/* Membrane voltages (mV) of every compartment, input order; cap >= total. */
+int sim_read_voltages(sim_t *sim, double *out_mV, int64_t cap);
+
+/* Gate states (m, h, n) of every compartment as double, input order. */
+int sim_read_gates(sim_t *sim, double *m, double *h, double *n, int64_t cap);
+
+/* Synaptic conductances (uS), synapse id order. */
+int sim_read_conductances(sim_t *sim, double *out_uS, int64_t cap);
+
+/* All spikes so far, sorted by (step, neuron). *n_total always receives the
+ * count; out == NULL only queries it; SIM_EINVAL if cap is too small
+ * (nothing written then). */
+int sim_spikes(sim_t *sim, sim_spike_t *out, int64_t cap, int64_t *n_total);
+
+/* Per-neuron kernel time in nanoseconds accumulated since create (or since
+ * the last reset), when record_timings is on. A neuron sharing a pack with
+ * others is charged the pack time split in proportion to compartments. */
+int sim_neuron_timings(sim_t *sim, double *out_ns, int64_t cap, int32_t reset);
+
+/* The 16 morphology features of every neuron (input order, row-major
+ * [n_neurons][16], float) that the cost model consumes. */
+int sim_features(sim_t *sim, float *out, int64_t cap);
+
+/* Device time of the epoch kernel (ms) and its launch count accumulated by
+ * sim_step while timing is on (set_timing(1)); off by default. */
+int sim_set_kernel_timing(sim_t *sim, int32_t on);
+int sim_kernel_time(sim_t *sim, double *ms, int64_t *launches);
+
+/* Launch configuration actually used (after autotuning), as text. */
+const char *sim_config_string(const sim_t *sim);
+
+void sim_destroy(sim_t *sim);
+
+/* Description of the last failure on `sim` (or of the last failed
+ * sim_create when sim is NULL). Library-owned; valid until the next call. */
+const char *sim_last_error(const sim_t *sim);
+
+/* ---------------------------------------------------------------------------
+ * Cost model: a 16-64-64-1 multilayer perceptron (ReLU) in float, trained on
+ * the GPU with the library's own forward, backward and Adam kernels. Inputs
+ * are the sim_features() rows; the model standardises them internally and
+ * predicts log(kernel time). Parameter vector layout (sim_mlp_nparams floats):
+ *   x_mean[16] x_std[16] W1[64][16] b1[64] W2[64][64] b2[64] W3[64] b3[1]
+ *   y_mean y_std
+ * ------------------------------------------------------------------------- */
+int64_t sim_mlp_nparams(void);
+
+/* Initialise parameters (He-uniform weights from `seed`, zero biases) and
+ * the standardisation from the training set. */
+int sim_mlp_init(float *params, const float *x, const float *y, int64_t n,
+                 uint64_t seed);
+
+/* Predictions (log time) for n feature rows. */
+int sim_mlp_forward(const float *params, const float *x, int64_t n,
+                    float *out);
+
+/* Mean squared error on standardised targets and its gradient with respect
+ * to the trainable parameters (the same layout; standardisation entries get
+ * zero gradient). */
+int sim_mlp_loss_grad(const float *params, const float *x, const float *y,
+                      int64_t n, float *loss, float *grad);
+
+/* Full-batch Adam training for `epochs` iterations; params updated in place;
+ * final loss returned. */
+int sim_mlp_train(float *params, const float *x, const float *y, int64_t n,
+                  int32_t epochs, float lr, float *final_loss);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

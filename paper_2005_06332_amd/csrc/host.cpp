@@ -1,0 +1,1277 @@
+// Host side of the simulator: input validation, morphology analysis
+// (branches, levels, features), packing of neurons into workgroup packs,
+// device layout, epoch launches (optionally replayed from a hipGraph) and the
+// C ABI of include/sim.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "internal.h"
+
+namespace mmh {
+hipError_t mlp_forward(const float *params, const float *x, int64_t n, float *out);
+hipError_t mlp_loss_grad(const float *params, const float *x, const float *t, int64_t n,
+                         float *loss, float *grad);
+hipError_t mlp_train(float *params, const float *x, const float *t, int64_t n, int epochs,
+                     float lr, float *final_loss);
+}  // namespace mmh
+
+using namespace mmh;
+
+namespace {
+
+std::string g_create_error;
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+Error fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return Error{code, buf};
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            throw fail(SIM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Morphology analysis of one neuron.
+// ---------------------------------------------------------------------------
+struct NeuronTopo {
+    int32_t n = 0;
+    std::vector<int32_t> b0, b1, bpar, height, depth;  // per branch
+    std::vector<int32_t> child_off, child;             // CSR of child branch ids
+    std::vector<int32_t> branch_of;                    // per compartment
+    int32_t max_height = 0, max_depth = 0;
+};
+
+void analyse(const int32_t *p, int32_t n, NeuronTopo &t) {
+    t.n = n;
+    std::vector<int32_t> nchild(n, 0);
+    for (int32_t i = 1; i < n; ++i) nchild[p[i]]++;
+    t.b0.clear();
+    t.b1.clear();
+    t.branch_of.assign(n, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        bool start = (i == 0) || !(p[i] == i - 1 && nchild[i - 1] == 1);
+        if (start) {
+            if (!t.b0.empty()) t.b1.push_back(i - 1);
+            t.b0.push_back(i);
+        }
+        t.branch_of[i] = (int32_t)t.b0.size() - 1;
+    }
+    t.b1.push_back(n - 1);
+    const int32_t nb = (int32_t)t.b0.size();
+    t.bpar.assign(nb, -1);
+    std::vector<int32_t> cnt(nb, 0);
+    for (int32_t b = 1; b < nb; ++b) {
+        t.bpar[b] = t.branch_of[p[t.b0[b]]];
+        cnt[t.bpar[b]]++;
+    }
+    t.child_off.assign(nb + 1, 0);
+    for (int32_t b = 0; b < nb; ++b) t.child_off[b + 1] = t.child_off[b] + cnt[b];
+    t.child.assign(t.child_off[nb], 0);
+    std::vector<int32_t> fill(nb, 0);
+    for (int32_t b = 1; b < nb; ++b) {
+        const int32_t q = t.bpar[b];
+        t.child[t.child_off[q] + fill[q]++] = b;  // ascending b, hence ascending base
+    }
+    t.height.assign(nb, 0);
+    for (int32_t b = nb - 1; b >= 0; --b)
+        for (int32_t c = t.child_off[b]; c < t.child_off[b + 1]; ++c)
+            t.height[b] = std::max(t.height[b], t.height[t.child[c]] + 1);
+    t.depth.assign(nb, 0);
+    for (int32_t b = 1; b < nb; ++b) t.depth[b] = t.depth[t.bpar[b]] + 1;
+    t.max_height = *std::max_element(t.height.begin(), t.height.end());
+    t.max_depth = *std::max_element(t.depth.begin(), t.depth.end());
+}
+
+void features(const NeuronTopo &t, const uint8_t *mech, int32_t nsyn, int32_t nseg,
+              float *f) {
+    const int32_t nb = (int32_t)t.b0.size();
+    int32_t maxlen = 0, leaves = 0, maxch = 0;
+    double sumsq = 0;
+    std::vector<int32_t> bw(t.max_height + 1, 0), fw(t.max_depth + 1, 0),
+        width(t.max_depth + 1, 0);
+    std::vector<int64_t> path(nb, 0);
+    int64_t crit = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t len = t.b1[b] - t.b0[b] + 1;
+        const int32_t nc = t.child_off[b + 1] - t.child_off[b];
+        maxlen = std::max(maxlen, len);
+        maxch = std::max(maxch, nc);
+        if (nc == 0) leaves++;
+        sumsq += (double)len * len;
+        bw[t.height[b]] = std::max(bw[t.height[b]], len + nc);
+        fw[t.depth[b]] = std::max(fw[t.depth[b]], len);
+        width[t.depth[b]]++;
+        path[b] = len + (t.bpar[b] >= 0 ? path[t.bpar[b]] : 0);
+        crit = std::max(crit, path[b]);
+    }
+    int64_t sbw = 0, sfw = 0;
+    for (int32_t v : bw) sbw += v;
+    for (int32_t v : fw) sfw += v;
+    int32_t nhh = 0;
+    for (int32_t i = 0; i < t.n; ++i) nhh += mech[i] ? 1 : 0;
+    f[0] = (float)t.n;
+    f[1] = (float)nb;
+    f[2] = (float)(t.max_depth + 1);
+    f[3] = (float)maxlen;
+    f[4] = (float)t.n / (float)nb;
+    f[5] = (float)crit;
+    f[6] = (float)sbw;
+    f[7] = (float)sfw;
+    f[8] = (float)leaves;
+    f[9] = (float)nsyn;
+    f[10] = (float)nseg;
+    f[11] = (float)nhh;
+    f[12] = (float)maxch;
+    f[13] = (float)*std::max_element(width.begin(), width.end());
+    f[14] = (float)(sumsq / nb);
+    f[15] = (float)(t.child_off[1] - t.child_off[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Launch variant and device buffers.
+// ---------------------------------------------------------------------------
+struct Variant {
+    int threads = 256;
+    int pack_comps = 1024;
+    int lds_limit = 64 * 1024;  // bytes of LDS per workgroup
+    int sched = SIM_SCHED_PERSISTENT;
+};
+
+template <typename X>
+struct DBuf {
+    X *p = nullptr;
+    int64_t n = 0;
+    void free_() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(int64_t count) {
+        free_();
+        n = count;
+        HIPCHK(hipMalloc((void **)&p, sizeof(X) * (count > 0 ? count : 1)));
+    }
+    void upload(const std::vector<X> &v) {
+        alloc((int64_t)v.size());
+        if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), sizeof(X) * v.size(), hipMemcpyHostToDevice));
+    }
+};
+
+}  // namespace
+
+struct sim {
+    // inputs (copied)
+    sim_params_t P{};
+    sim_channels_t CH{};
+    int32_t N = 0;
+    int64_t C = 0, S = 0;
+    std::vector<int64_t> off;
+    std::vector<int32_t> parent, detector, pre, post, pcomp, delay;
+    std::vector<double> length, diam, iext, weight;
+    std::vector<uint8_t> mech;
+    std::vector<float> cost_model;
+    int precision = 1;
+    int E = 40;
+    int tsize = 4;  // sizeof gating type
+
+    // analysis
+    std::vector<NeuronTopo> topo;
+    std::vector<float> feat;           // [N][16]
+    std::vector<int32_t> nsyn_of;      // synapses per post neuron
+    std::vector<int64_t> syn_by_post;  // synapse ids grouped by post, ascending id
+    std::vector<int64_t> syn_post_off; // [N+1]
+    std::vector<double> cost;          // packing cost per neuron
+
+    // layout
+    Variant var;
+    std::vector<int32_t> order;        // packed position -> input neuron
+    std::vector<int64_t> comp_perm;    // packed compartment -> input compartment
+    std::vector<int64_t> syn_perm;     // packed synapse -> input synapse id
+    std::vector<PackDesc> packs;
+    std::vector<double> pack_cost;
+    std::vector<int32_t> pack_of_neuron;  // input neuron -> pack
+    std::vector<int32_t> wg_off, wg_list;
+    int n_wg = 0;
+    size_t lds_bytes = 0;
+    int64_t scratch_bytes = 0;
+    int max_lds = 64 * 1024;
+    int n_cu = 256;
+
+    // device
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    DBuf<PackDesc> d_packs;
+    DBuf<int32_t> d_wg_off, d_wg_list, d_spre, d_sdelay, d_nid, d_ndet, d_lvl, d_lparent;
+    DBuf<double> d_V, d_cdt, d_G, d_e, d_dc, d_len, d_diam, d_w64, d_iext64, d_q;
+    DBuf<char> d_gm, d_gh, d_gn, d_af, d_sg, d_sw, d_niext, d_scratch;
+    DBuf<uint32_t> d_topo;
+    DBuf<uint16_t> d_scomp, d_sseg, d_chl, d_sched;
+    DBuf<Branch> d_br;
+    DBuf<int64_t> d_ncomp0, d_epoch;
+    DBuf<uint64_t> d_hist, d_ptime;
+    int64_t hist_epochs = 0;
+    double q = 0;
+
+    // time
+    int64_t step = 0;
+    hipGraph_t graph1 = nullptr, graphK = nullptr;
+    hipGraphExec_t exec1 = nullptr, execK = nullptr;
+    int graphK_epochs = 8;
+    bool kt_on = false;
+    double kt_ms = 0;
+    int64_t kt_launches = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double tick_ns = 10.0;
+
+    std::string err, config;
+};
+
+namespace {
+
+void set_error(sim_t *s, const Error &e) {
+    if (s)
+        s->err = e.msg;
+    else
+        g_create_error = e.msg;
+}
+
+// ---------------------------------------------------------------------------
+// Validation: everything is checked before any device allocation.
+// ---------------------------------------------------------------------------
+void validate(const sim_params_t *P, const sim_morphology_t *M, const sim_channels_t *CH,
+              const sim_synapses_t *SY) {
+    if (!P || !M || !CH || !SY) throw fail(SIM_EINVAL, "null argument");
+    if (!(P->dt_ms > 0) || !std::isfinite(P->dt_ms)) throw fail(SIM_EINVAL, "dt_ms must be > 0");
+    if (!(P->theta == 0.5 || P->theta == 1.0))
+        throw fail(SIM_EINVAL, "theta must be 0.5 or 1.0 (got %g)", P->theta);
+    if (!(P->tau_syn_ms > 0) || !std::isfinite(P->tau_syn_ms))
+        throw fail(SIM_EINVAL, "tau_syn_ms must be > 0");
+    for (double v : {P->e_syn_mV, P->v_thresh_mV, P->v_init_mV, CH->cm_uF_cm2, CH->ra_ohm_cm,
+                     CH->gnabar, CH->gkbar, CH->gl, CH->ena, CH->ek, CH->el, CH->g_pas, CH->e_pas})
+        if (!std::isfinite(v)) throw fail(SIM_EINVAL, "non-finite parameter");
+    if (!(CH->cm_uF_cm2 > 0) || !(CH->ra_ohm_cm > 0))
+        throw fail(SIM_EINVAL, "cm and ra must be > 0");
+    if (P->precision != SIM_FP64 && P->precision != SIM_FP32_GATING)
+        throw fail(SIM_EINVAL, "unknown precision %d", P->precision);
+    if (P->packing < SIM_PACK_PLAIN || P->packing > SIM_PACK_LEARNED)
+        throw fail(SIM_EINVAL, "unknown packing %d", P->packing);
+    if (P->sched < SIM_SCHED_AUTO || P->sched > SIM_SCHED_DISPATCH)
+        throw fail(SIM_EINVAL, "unknown sched %d", P->sched);
+    if (P->threads != 0 && (P->threads < 64 || P->threads > 1024 || P->threads % 64))
+        throw fail(SIM_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
+    if (P->pack_comps < 0 || P->lds_comps < 0) throw fail(SIM_EINVAL, "negative size");
+    if (M->n_neurons < 1) throw fail(SIM_EINVAL, "n_neurons must be >= 1");
+    if (!M->comp_offset || !M->parent || !M->length_um || !M->diam_um || !M->mech ||
+        !M->detector || !M->i_ext_nA)
+        throw fail(SIM_EINVAL, "null morphology array");
+    const int32_t N = M->n_neurons;
+    if (M->comp_offset[0] != 0) throw fail(SIM_EINVAL, "comp_offset[0] must be 0");
+    for (int32_t j = 0; j < N; ++j) {
+        const int64_t b = M->comp_offset[j], e = M->comp_offset[j + 1];
+        const int64_t n = e - b;
+        if (n < 1) throw fail(SIM_EINVAL, "neuron %d has no compartments", j);
+        if (n > 32767) throw fail(SIM_EINVAL, "neuron %d has %lld > 32767 compartments", j, (long long)n);
+        if (M->parent[b] != -1) throw fail(SIM_EINVAL, "neuron %d: parent[0] must be -1", j);
+        for (int64_t i = 1; i < n; ++i) {
+            const int32_t p = M->parent[b + i];
+            if (p < 0 || p >= i)
+                throw fail(SIM_EINVAL, "neuron %d compartment %lld: parent %d not in [0, %lld)", j,
+                           (long long)i, p, (long long)i);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            const double L = M->length_um[b + i], d = M->diam_um[b + i];
+            if (!(L > 0) || !(d > 0) || !std::isfinite(L) || !std::isfinite(d))
+                throw fail(SIM_EINVAL, "neuron %d compartment %lld: bad geometry", j, (long long)i);
+            if (M->mech[b + i] > 1) throw fail(SIM_EINVAL, "mech must be 0 or 1");
+        }
+        if (M->detector[j] < 0 || M->detector[j] >= n)
+            throw fail(SIM_EINVAL, "neuron %d: detector out of range", j);
+        if (!std::isfinite(M->i_ext_nA[j])) throw fail(SIM_EINVAL, "non-finite i_ext");
+    }
+    if (SY->n < 0) throw fail(SIM_EINVAL, "negative synapse count");
+    if (SY->n > 0 && (!SY->pre || !SY->post || !SY->post_comp || !SY->delay_steps || !SY->weight_uS))
+        throw fail(SIM_EINVAL, "null synapse array");
+    int64_t mind = INT64_MAX;
+    for (int64_t k = 0; k < SY->n; ++k) {
+        const int32_t a = SY->pre[k], b = SY->post[k];
+        if (a < 0 || a >= N || b < 0 || b >= N) throw fail(SIM_EINVAL, "synapse %lld: neuron out of range", (long long)k);
+        const int64_t nb = M->comp_offset[b + 1] - M->comp_offset[b];
+        if (SY->post_comp[k] < 0 || SY->post_comp[k] >= nb)
+            throw fail(SIM_EINVAL, "synapse %lld: compartment out of range", (long long)k);
+        if (SY->delay_steps[k] < 1) throw fail(SIM_EINVAL, "synapse %lld: delay must be >= 1 step", (long long)k);
+        if (!(SY->weight_uS[k] >= 0) || !std::isfinite(SY->weight_uS[k]))
+            throw fail(SIM_EINVAL, "synapse %lld: weight must be finite and >= 0", (long long)k);
+        mind = std::min<int64_t>(mind, SY->delay_steps[k]);
+    }
+    if (P->epoch_steps < 0 || P->epoch_steps > 64)
+        throw fail(SIM_EINVAL, "epoch_steps must be in [0, 64]");
+    if (P->epoch_steps > 0 && SY->n > 0 && P->epoch_steps > mind)
+        throw fail(SIM_EINVAL, "epoch_steps %d exceeds the smallest delay %lld", P->epoch_steps,
+                   (long long)mind);
+    if (P->packing == SIM_PACK_LEARNED && P->cost_model) {
+        for (int64_t i = 0; i < kMlpParams; ++i)
+            if (!std::isfinite(P->cost_model[i])) throw fail(SIM_EINVAL, "non-finite cost model");
+    }
+}
+
+void copy_inputs(sim_t *s, const sim_params_t *P, const sim_morphology_t *M,
+                 const sim_channels_t *CH, const sim_synapses_t *SY) {
+    s->P = *P;
+    s->CH = *CH;
+    s->N = M->n_neurons;
+    s->C = M->comp_offset[s->N];
+    s->S = SY->n;
+    s->off.assign(M->comp_offset, M->comp_offset + s->N + 1);
+    s->parent.assign(M->parent, M->parent + s->C);
+    s->length.assign(M->length_um, M->length_um + s->C);
+    s->diam.assign(M->diam_um, M->diam_um + s->C);
+    s->mech.assign(M->mech, M->mech + s->C);
+    s->detector.assign(M->detector, M->detector + s->N);
+    s->iext.assign(M->i_ext_nA, M->i_ext_nA + s->N);
+    if (s->S) {
+        s->pre.assign(SY->pre, SY->pre + s->S);
+        s->post.assign(SY->post, SY->post + s->S);
+        s->pcomp.assign(SY->post_comp, SY->post_comp + s->S);
+        s->delay.assign(SY->delay_steps, SY->delay_steps + s->S);
+        s->weight.assign(SY->weight_uS, SY->weight_uS + s->S);
+    }
+    if (P->cost_model) s->cost_model.assign(P->cost_model, P->cost_model + kMlpParams);
+    s->precision = P->precision;
+    s->tsize = P->precision == SIM_FP64 ? 8 : 4;
+    int64_t mind = 64;
+    for (int64_t k = 0; k < s->S; ++k) mind = std::min<int64_t>(mind, s->delay[k]);
+    s->E = P->epoch_steps > 0 ? P->epoch_steps : (int)mind;
+}
+
+void analyse_all(sim_t *s) {
+    s->topo.resize(s->N);
+    s->nsyn_of.assign(s->N, 0);
+    for (int64_t k = 0; k < s->S; ++k) s->nsyn_of[s->post[k]]++;
+    s->syn_post_off.assign(s->N + 1, 0);
+    for (int32_t j = 0; j < s->N; ++j) s->syn_post_off[j + 1] = s->syn_post_off[j] + s->nsyn_of[j];
+    s->syn_by_post.assign(s->S, 0);
+    std::vector<int64_t> fill(s->N, 0);
+    for (int64_t k = 0; k < s->S; ++k) {
+        const int32_t j = s->post[k];
+        s->syn_by_post[s->syn_post_off[j] + fill[j]++] = k;
+    }
+    s->feat.assign((size_t)s->N * kFeat, 0.0f);
+    std::vector<int32_t> seen;
+    for (int32_t j = 0; j < s->N; ++j) {
+        const int64_t b = s->off[j];
+        const int32_t n = (int32_t)(s->off[j + 1] - b);
+        analyse(s->parent.data() + b, n, s->topo[j]);
+        // distinct target compartments
+        seen.clear();
+        for (int64_t q = s->syn_post_off[j]; q < s->syn_post_off[j + 1]; ++q)
+            seen.push_back(s->pcomp[s->syn_by_post[q]]);
+        std::sort(seen.begin(), seen.end());
+        const int32_t nseg = (int32_t)(std::unique(seen.begin(), seen.end()) - seen.begin());
+        features(s->topo[j], s->mech.data() + b, s->nsyn_of[j], nseg, &s->feat[(size_t)j * kFeat]);
+    }
+}
+
+void compute_cost(sim_t *s) {
+    s->cost.assign(s->N, 0.0);
+    const bool learned = s->P.packing == SIM_PACK_LEARNED && !s->cost_model.empty();
+    if (learned) {
+        std::vector<float> pred(s->N);
+        hipError_t e = mlp_forward(s->cost_model.data(), s->feat.data(), s->N, pred.data());
+        if (e != hipSuccess) throw fail(SIM_EDEVICE, "cost model inference failed: %s", hipGetErrorString(e));
+        for (int32_t j = 0; j < s->N; ++j) s->cost[j] = std::exp((double)pred[j]);
+    } else {
+        for (int32_t j = 0; j < s->N; ++j) s->cost[j] = (double)(s->off[j + 1] - s->off[j]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Packing and layout.
+// ---------------------------------------------------------------------------
+int64_t state_bytes(const sim_t *s, int64_t n, int64_t ns, int64_t k) {
+    return s->tsize == 8 ? pack_state_bytes<double>(n, ns, k) : pack_state_bytes<float>(n, ns, k);
+}
+
+void build_layout(sim_t *s, const Variant &v) {
+    s->var = v;
+    const int32_t N = s->N;
+    // neuron order
+    s->order.resize(N);
+    std::iota(s->order.begin(), s->order.end(), 0);
+    if (s->P.packing != SIM_PACK_PLAIN)
+        std::stable_sort(s->order.begin(), s->order.end(),
+                         [&](int32_t a, int32_t b) { return s->cost[a] > s->cost[b]; });
+    // packs: consecutive neurons (in that order) up to pack_comps compartments
+    struct P0 {
+        int32_t first, count;
+        int64_t ncomp, nsyn;
+        int32_t nbr;
+    };
+    std::vector<P0> pk;
+    {
+        P0 cur{0, 0, 0, 0, 0};
+        for (int32_t q = 0; q < N; ++q) {
+            const int32_t j = s->order[q];
+            const int64_t n = s->off[j + 1] - s->off[j];
+            const int32_t nb = (int32_t)s->topo[j].b0.size();
+            const bool fits = cur.count == 0 ||
+                              (cur.ncomp + n <= v.pack_comps && cur.count < 1024 &&
+                               cur.ncomp + n <= 32766 && cur.nbr + nb <= 32766);
+            if (!fits) {
+                pk.push_back(cur);
+                cur = P0{q, 0, 0, 0, 0};
+            }
+            cur.count++;
+            cur.ncomp += n;
+            cur.nsyn += s->nsyn_of[j];
+            cur.nbr += nb;
+        }
+        pk.push_back(cur);
+    }
+    const int npk = (int)pk.size();
+    s->packs.assign(npk, PackDesc{});
+    s->pack_cost.assign(npk, 0.0);
+    s->pack_of_neuron.assign(N, 0);
+
+    std::vector<uint32_t> topo;
+    std::vector<int32_t> lparent, nid, ndet, lvl;
+    std::vector<double> len, dia, w64, iext64;
+    std::vector<int64_t> ncomp0;
+    std::vector<int32_t> spre, sdel;
+    std::vector<uint16_t> scomp, sseg, chl, sched;
+    std::vector<Branch> brs;
+    topo.reserve(s->C);
+    lparent.reserve(s->C);
+    len.reserve(s->C);
+    dia.reserve(s->C);
+    s->comp_perm.clear();
+    s->comp_perm.reserve(s->C);
+    s->syn_perm.clear();
+    s->syn_perm.reserve(s->S);
+    int64_t lds_max = 0, scratch = 0;
+    std::vector<std::pair<int64_t, int64_t>> segs;  // (local comp, synapse id)
+
+    for (int p = 0; p < npk; ++p) {
+        PackDesc d{};
+        d.comp0 = (int64_t)topo.size();
+        d.syn0 = (int64_t)spre.size();
+        d.ncomp = (int32_t)pk[p].ncomp;
+        d.nsyn = (int32_t)pk[p].nsyn;
+        d.neur0 = pk[p].first;
+        d.nneur = pk[p].count;
+        d.br0 = (int32_t)brs.size();
+        d.nbr = pk[p].nbr;
+        d.ch0 = (int32_t)chl.size();
+        d.lv0 = (int32_t)lvl.size();
+        d.sc0 = (int32_t)sched.size();
+        int32_t maxh = 0, maxd = 0;
+        int32_t comp_base = 0, br_base = 0;
+        segs.clear();
+        std::vector<int32_t> bh, bd;  // height, depth of pack-local branches
+        for (int32_t k = 0; k < pk[p].count; ++k) {
+            const int32_t q = pk[p].first + k;
+            const int32_t j = s->order[q];
+            s->pack_of_neuron[j] = p;
+            s->pack_cost[p] += s->cost[j];
+            const NeuronTopo &t = s->topo[j];
+            const int64_t b = s->off[j];
+            const int32_t n = t.n;
+            const int32_t nb = (int32_t)t.b0.size();
+            maxh = std::max(maxh, t.max_height);
+            maxd = std::max(maxd, t.max_depth);
+            // branch-end marker per local compartment
+            std::vector<int32_t> end_branch(n, -1);
+            for (int32_t bb = 0; bb < nb; ++bb) end_branch[t.b1[bb]] = bb;
+            for (int32_t i = 0; i < n; ++i) {
+                const bool root = i == 0;
+                const uint32_t par = root ? (uint32_t)k : (uint32_t)(comp_base + s->parent[b + i]);
+                const uint32_t bid = end_branch[i] >= 0 ? (uint32_t)(br_base + end_branch[i]) : kNone;
+                topo.push_back(make_topo(par, s->mech[b + i] != 0, bid, root));
+                lparent.push_back(s->parent[b + i]);
+                len.push_back(s->length[b + i]);
+                dia.push_back(s->diam[b + i]);
+                s->comp_perm.push_back(b + i);
+            }
+            for (int32_t bb = 0; bb < nb; ++bb) {
+                Branch r;
+                r.b0 = (uint16_t)(comp_base + t.b0[bb]);
+                r.b1 = (uint16_t)(comp_base + t.b1[bb]);
+                r.child0 = (uint16_t)(chl.size() - d.ch0);
+                r.nchild = (uint16_t)(t.child_off[bb + 1] - t.child_off[bb]);
+                for (int32_t c = t.child_off[bb]; c < t.child_off[bb + 1]; ++c)
+                    chl.push_back((uint16_t)(comp_base + t.b0[t.child[c]]));
+                brs.push_back(r);
+                bh.push_back(t.height[bb]);
+                bd.push_back(t.depth[bb]);
+            }
+            nid.push_back(j);
+            ndet.push_back(comp_base + s->detector[j]);
+            iext64.push_back(s->iext[j]);
+            ncomp0.push_back(d.comp0 + comp_base);
+            for (int64_t qq = s->syn_post_off[j]; qq < s->syn_post_off[j + 1]; ++qq) {
+                const int64_t sid = s->syn_by_post[qq];
+                segs.emplace_back((int64_t)comp_base + s->pcomp[sid], sid);
+            }
+            comp_base += n;
+            br_base += nb;
+        }
+        if (d.ch0 + (int64_t)(chl.size() - d.ch0) > INT32_MAX) throw fail(SIM_ENOMEM, "child list too large");
+        if ((int64_t)chl.size() - d.ch0 > 65535) throw fail(SIM_EINVAL, "pack child list too large");
+        // synapses by (local compartment, id)
+        std::sort(segs.begin(), segs.end());
+        for (size_t u = 0; u < segs.size(); ++u) {
+            const int64_t sid = segs[u].second;
+            s->syn_perm.push_back(sid);
+            spre.push_back(s->pre[sid]);
+            sdel.push_back(s->delay[sid]);
+            w64.push_back(s->weight[sid]);
+            scomp.push_back((uint16_t)segs[u].first);
+            int32_t run = 0;
+            if (u == 0 || segs[u].first != segs[u - 1].first) {
+                size_t w = u;
+                while (w < segs.size() && segs[w].first == segs[u].first) ++w;
+                run = (int32_t)(w - u);
+            }
+            if (run > 65535) throw fail(SIM_EINVAL, "too many synapses on one compartment");
+            sseg.push_back((uint16_t)run);
+        }
+        // levels: branches by height (backward), by depth (forward)
+        d.nbw = maxh + 1;
+        d.nfw = maxd + 1;
+        const int32_t nbr = d.nbr;
+        std::vector<int32_t> cnt(std::max(d.nbw, d.nfw) + 1, 0);
+        lvl.push_back(0);
+        for (int h = 0; h < d.nbw; ++h) {
+            for (int32_t bb = 0; bb < nbr; ++bb)
+                if (bh[bb] == h) sched.push_back((uint16_t)bb);
+            lvl.push_back((int32_t)(sched.size() - d.sc0));
+        }
+        lvl.push_back(0);
+        for (int h = 0; h < d.nfw; ++h) {
+            for (int32_t bb = 0; bb < nbr; ++bb)
+                if (bd[bb] == h) sched.push_back((uint16_t)bb);
+            lvl.push_back((int32_t)(sched.size() - d.sc0 - nbr));
+        }
+        const int64_t bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
+        if (bytes <= v.lds_limit) {
+            d.global_mem = 0;
+            lds_max = std::max(lds_max, bytes);
+        } else {
+            d.global_mem = 1;
+            scratch = std::max(scratch, bytes);
+        }
+        s->packs[p] = d;
+    }
+    ncomp0.push_back((int64_t)topo.size());
+    s->lds_bytes = (size_t)std::max<int64_t>(lds_max, 256);
+    s->scratch_bytes = scratch;
+
+    // workgroup lists
+    s->wg_off.clear();
+    s->wg_list.clear();
+    int sched_mode = v.sched;
+    if (s->P.packing == SIM_PACK_PLAIN) sched_mode = SIM_SCHED_DISPATCH;
+    if (sched_mode == SIM_SCHED_DISPATCH) {
+        s->n_wg = npk;
+        for (int p = 0; p <= npk; ++p) s->wg_off.push_back(p);
+        for (int p = 0; p < npk; ++p) s->wg_list.push_back(p);
+    } else {
+        // resident workgroups per CU from the LDS footprint and the thread count
+        const int by_lds = std::max(1, (int)(s->max_lds / std::max<size_t>(s->lds_bytes, 1)));
+        const int by_thr = std::max(1, 2048 / v.threads);
+        const int per_cu = std::max(1, std::min(by_lds, by_thr));
+        s->n_wg = std::max(1, std::min(npk, per_cu * s->n_cu));
+        // LPT: packs by decreasing cost, each to the least loaded workgroup
+        std::vector<int32_t> byc(npk);
+        std::iota(byc.begin(), byc.end(), 0);
+        std::stable_sort(byc.begin(), byc.end(),
+                         [&](int32_t a, int32_t b) { return s->pack_cost[a] > s->pack_cost[b]; });
+        using QE = std::pair<double, int32_t>;
+        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> heap;
+        for (int w = 0; w < s->n_wg; ++w) heap.push({0.0, w});
+        std::vector<std::vector<int32_t>> lists(s->n_wg);
+        for (int32_t p : byc) {
+            QE top = heap.top();
+            heap.pop();
+            lists[top.second].push_back(p);
+            heap.push({top.first + s->pack_cost[p], top.second});
+        }
+        s->wg_off.push_back(0);
+        for (int w = 0; w < s->n_wg; ++w) {
+            for (int32_t p : lists[w]) s->wg_list.push_back(p);
+            s->wg_off.push_back((int32_t)s->wg_list.size());
+        }
+    }
+
+    // device upload
+    s->d_packs.upload(s->packs);
+    s->d_wg_off.upload(s->wg_off);
+    s->d_wg_list.upload(s->wg_list);
+    s->d_topo.upload(topo);
+    s->d_lparent.upload(lparent);
+    s->d_len.upload(len);
+    s->d_diam.upload(dia);
+    s->d_ncomp0.upload(ncomp0);
+    s->d_nid.upload(nid);
+    s->d_ndet.upload(ndet);
+    s->d_iext64.upload(iext64);
+    s->d_spre.upload(spre);
+    s->d_sdelay.upload(sdel);
+    s->d_w64.upload(w64);
+    s->d_scomp.upload(scomp);
+    s->d_sseg.upload(sseg);
+    s->d_br.upload(brs);
+    s->d_chl.upload(chl);
+    s->d_lvl.upload(lvl);
+    s->d_sched.upload(sched);
+    const int64_t C = s->C, S = s->S;
+    s->d_V.alloc(C);
+    s->d_cdt.alloc(C);
+    s->d_G.alloc(C);
+    s->d_e.alloc(C);
+    s->d_dc.alloc(C);
+    s->d_gm.alloc(C * s->tsize);
+    s->d_gh.alloc(C * s->tsize);
+    s->d_gn.alloc(C * s->tsize);
+    s->d_af.alloc(C * s->tsize);
+    s->d_sg.alloc(S * s->tsize);
+    s->d_sw.alloc(S * s->tsize);
+    s->d_niext.alloc((int64_t)N * s->tsize);
+    s->d_q.alloc(1);
+    s->d_scratch.alloc(256);
+    s->d_ptime.alloc(npk);
+    HIPCHK(hipMemset(s->d_ptime.p, 0, sizeof(uint64_t) * npk));
+}
+
+void init_state(sim_t *s) {
+    SetupArgs a{};
+    a.n_neurons = s->N;
+    a.ncomp0 = s->d_ncomp0.p;
+    a.lparent = s->d_lparent.p;
+    a.length = s->d_len.p;
+    a.diam = s->d_diam.p;
+    a.cm = s->CH.cm_uF_cm2;
+    a.ra = s->CH.ra_ohm_cm;
+    a.dt = s->P.dt_ms;
+    a.theta = s->P.theta;
+    a.v_init = s->P.v_init_mV;
+    a.cdt = s->d_cdt.p;
+    a.G = s->d_G.p;
+    a.e = s->d_e.p;
+    a.dc = s->d_dc.p;
+    a.V = s->d_V.p;
+    a.af = s->d_af.p;
+    a.gm = s->d_gm.p;
+    a.gh = s->d_gh.p;
+    a.gn = s->d_gn.p;
+    a.q_out = s->d_q.p;
+    a.tau = s->P.tau_syn_ms;
+    HIPCHK(launch_setup(a, s->precision == SIM_FP64 ? 0 : 1, s->stream));
+    const int pr = s->precision == SIM_FP64 ? 0 : 1;
+    HIPCHK(launch_decay_weights_convert(s->d_w64.p, s->d_sw.p, s->S, pr, s->stream));
+    HIPCHK(launch_decay_weights_convert(s->d_iext64.p, s->d_niext.p, s->N, pr, s->stream));
+    if (s->S) HIPCHK(hipMemsetAsync(s->d_sg.p, 0, s->S * s->tsize, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpy(&s->q, s->d_q.p, sizeof(double), hipMemcpyDeviceToHost));
+    s->step = 0;
+    if (s->d_hist.p && s->d_hist.n) HIPCHK(launch_fill_u64(s->d_hist.p, s->d_hist.n, 0, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+void destroy_graphs(sim_t *s) {
+    if (s->exec1) (void)hipGraphExecDestroy(s->exec1);
+    if (s->execK) (void)hipGraphExecDestroy(s->execK);
+    if (s->graph1) (void)hipGraphDestroy(s->graph1);
+    if (s->graphK) (void)hipGraphDestroy(s->graphK);
+    s->exec1 = s->execK = nullptr;
+    s->graph1 = s->graphK = nullptr;
+}
+
+void ensure_hist(sim_t *s, int64_t epochs_needed) {
+    if (epochs_needed <= s->hist_epochs) return;
+    int64_t cap = std::max<int64_t>(epochs_needed, std::max<int64_t>(16, s->hist_epochs * 2));
+    DBuf<uint64_t> nb;
+    nb.alloc(cap * s->N);
+    HIPCHK(launch_fill_u64(nb.p, nb.n, 0, s->stream));
+    if (s->d_hist.p && s->hist_epochs)
+        HIPCHK(hipMemcpyAsync(nb.p, s->d_hist.p, sizeof(uint64_t) * s->hist_epochs * s->N,
+                              hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->d_hist.free_();
+    s->d_hist = nb;
+    s->hist_epochs = cap;
+    destroy_graphs(s);
+}
+
+EpochArgs make_args(sim_t *s) {
+    EpochArgs a{};
+    a.packs = s->d_packs.p;
+    a.wg_off = s->d_wg_off.p;
+    a.wg_list = s->d_wg_list.p;
+    a.V = s->d_V.p;
+    a.gm = s->d_gm.p;
+    a.gh = s->d_gh.p;
+    a.gn = s->d_gn.p;
+    a.topo = s->d_topo.p;
+    a.cdt = s->d_cdt.p;
+    a.G = s->d_G.p;
+    a.e = s->d_e.p;
+    a.dc = s->d_dc.p;
+    a.af = s->d_af.p;
+    a.sg = s->d_sg.p;
+    a.sw = s->d_sw.p;
+    a.spre = s->d_spre.p;
+    a.sdelay = s->d_sdelay.p;
+    a.scomp = s->d_scomp.p;
+    a.sseg = s->d_sseg.p;
+    a.nid = s->d_nid.p;
+    a.ndet = s->d_ndet.p;
+    a.niext = s->d_niext.p;
+    a.br = s->d_br.p;
+    a.chl = s->d_chl.p;
+    a.lvl = s->d_lvl.p;
+    a.sched = s->d_sched.p;
+    a.hist = s->d_hist.p;
+    a.n_neurons = s->N;
+    a.E = s->E;
+    a.scratch = s->d_scratch.p;
+    a.scratch_stride = 0;
+    a.omt = 1.0 - s->P.theta;
+    a.v_thresh = s->P.v_thresh_mV;
+    a.gnabar = s->CH.gnabar;
+    a.gkbar = s->CH.gkbar;
+    a.gl = s->CH.gl;
+    a.ena = s->CH.ena;
+    a.ek = s->CH.ek;
+    a.el = s->CH.el;
+    a.g_pas = s->CH.g_pas;
+    a.e_pas = s->CH.e_pas;
+    a.e_syn = s->P.e_syn_mV;
+    a.dt = s->P.dt_ms;
+    a.q = s->q;
+    a.pack_time = s->P.record_timings ? s->d_ptime.p : nullptr;
+    return a;
+}
+
+}  // namespace
+
+namespace {
+
+// Global packs need disjoint scratch slices even when one workgroup runs
+// several of them in sequence: the slice is chosen per pack from its ordinal.
+// The offsets are folded into the pack table's `global_mem` field (1 + slice
+// index in units of the largest global pack).
+void assign_scratch(sim_t *s) {
+    int64_t maxb = 0;
+    int32_t count = 0;
+    for (auto &d : s->packs)
+        if (d.global_mem) {
+            maxb = std::max(maxb, state_bytes(s, d.ncomp, d.nsyn, d.nneur));
+            d.global_mem = 1 + count++;
+        }
+    if (count) {
+        s->d_scratch.alloc(maxb * count);
+        s->scratch_bytes = maxb;
+        HIPCHK(hipMemcpy(s->d_packs.p, s->packs.data(), sizeof(PackDesc) * s->packs.size(),
+                         hipMemcpyHostToDevice));
+    }
+}
+
+void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
+    EpochArgs a = make_args(s);
+    a.epoch = epoch;
+    a.epoch_ptr = use_ptr ? s->d_epoch.p : nullptr;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.scratch_stride = s->scratch_bytes;
+    HIPCHK(launch_epoch(a, s->precision == SIM_FP64 ? 0 : 1, s->n_wg, s->var.threads, s->lds_bytes,
+                        s->stream));
+}
+
+void capture(sim_t *s, int epochs, hipGraph_t &g, hipGraphExec_t &ex) {
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < epochs; ++k) {
+        launch_range(s, 0, 0, s->E, true);
+        hipError_t e = launch_advance(s->d_epoch.p, s->stream);
+        if (e != hipSuccess) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(s->stream, &dummy);
+            throw fail(SIM_EDEVICE, "capture failed: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamEndCapture(s->stream, &g));
+    HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+}
+
+void run_steps(sim_t *s, int64_t n) {
+    if (n <= 0) return;
+    const int E = s->E;
+    ensure_hist(s, (s->step + n + E - 1) / E + 1);
+    while (n > 0) {
+        const int64_t ep = s->step / E;
+        const int t0 = (int)(s->step % E);
+        const int64_t full = (t0 == 0) ? n / E : 0;
+        if (full > 0 && s->P.use_graph && !s->kt_on) {
+            if (!s->exec1) capture(s, 1, s->graph1, s->exec1);
+            if (!s->execK) capture(s, s->graphK_epochs, s->graphK, s->execK);
+            HIPCHK(hipMemcpy(s->d_epoch.p, &ep, sizeof(int64_t), hipMemcpyHostToDevice));
+            int64_t left = full;
+            while (left >= s->graphK_epochs) {
+                HIPCHK(hipGraphLaunch(s->execK, s->stream));
+                left -= s->graphK_epochs;
+            }
+            while (left > 0) {
+                HIPCHK(hipGraphLaunch(s->exec1, s->stream));
+                left -= 1;
+            }
+            s->step += full * E;
+            n -= full * E;
+            continue;
+        }
+        const int t1 = (int)std::min<int64_t>(E, t0 + n);
+        if (s->kt_on) HIPCHK(hipEventRecord(s->ev0, s->stream));
+        launch_range(s, ep, t0, t1, false);
+        if (s->kt_on) {
+            HIPCHK(hipEventRecord(s->ev1, s->stream));
+            HIPCHK(hipEventSynchronize(s->ev1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+            s->kt_ms += ms;
+            s->kt_launches++;
+        }
+        s->step += t1 - t0;
+        n -= t1 - t0;
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+std::string describe(const sim_t *s) {
+    char buf[512];
+    int nglob = 0;
+    for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
+    snprintf(buf, sizeof buf,
+             "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d wg=%d "
+             "lds_bytes=%zu E=%d precision=%s packing=%s",
+             s->var.threads, s->var.pack_comps, s->var.lds_limit,
+             (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
+                                                                                    : "persistent",
+             s->packs.size(), nglob, s->n_wg, s->lds_bytes, s->E,
+             s->precision == SIM_FP64 ? "fp64" : "fp32-gating",
+             s->P.packing == SIM_PACK_PLAIN ? "plain"
+             : s->P.packing == SIM_PACK_COUNT ? "count"
+             : s->cost_model.empty() ? "learned(fallback count)" : "learned");
+    return buf;
+}
+
+void apply_variant(sim_t *s, const Variant &v) {
+    destroy_graphs(s);
+    build_layout(s, v);
+    assign_scratch(s);
+    init_state(s);
+    s->config = describe(s);
+}
+
+// Autotuning: time one epoch of each candidate from the initial state, keep
+// the fastest, then re-initialise. Candidates never change results: they only
+// move neurons between workgroups or memory spaces.
+void autotune(sim_t *s, Variant base) {
+    std::vector<Variant> cand;
+    for (int thr : {128, 256})
+        for (int pc : {512, 1024, 2048})
+            for (int lds : {48 * 1024, 96 * 1024})
+                for (int sc : {SIM_SCHED_PERSISTENT, SIM_SCHED_DISPATCH}) {
+                    Variant v = base;
+                    v.threads = thr;
+                    v.pack_comps = pc;
+                    v.lds_limit = std::min(lds, s->max_lds);
+                    v.sched = sc;
+                    cand.push_back(v);
+                }
+    double best = 1e30;
+    Variant bestv = base;
+    for (const Variant &v : cand) {
+        apply_variant(s, v);
+        ensure_hist(s, 2);
+        launch_range(s, 0, 0, s->E, false);  // warm-up
+        HIPCHK(hipStreamSynchronize(s->stream));
+        HIPCHK(hipEventRecord(s->ev0, s->stream));
+        launch_range(s, 0, 0, s->E, false);
+        HIPCHK(hipEventRecord(s->ev1, s->stream));
+        HIPCHK(hipEventSynchronize(s->ev1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+        if (ms < best) {
+            best = ms;
+            bestv = v;
+        }
+    }
+    apply_variant(s, bestv);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void sim_default_params(sim_params_t *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->dt_ms = 0.025;
+    p->theta = 0.5;
+    p->tau_syn_ms = 2.0;
+    p->e_syn_mV = 0.0;
+    p->v_thresh_mV = 0.0;
+    p->v_init_mV = -65.0;
+    p->precision = SIM_FP32_GATING;
+    p->packing = SIM_PACK_COUNT;
+    p->sched = SIM_SCHED_AUTO;
+    p->use_graph = 1;
+}
+
+int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
+               const sim_channels_t *channels, const sim_synapses_t *syn, sim_t **out) {
+    if (!out) {
+        g_create_error = "null output pointer";
+        return SIM_EINVAL;
+    }
+    *out = nullptr;
+    sim_t *s = nullptr;
+    try {
+        validate(params, morph, channels, syn);
+        s = new sim_t();
+        copy_inputs(s, params, morph, channels, syn);
+        analyse_all(s);
+        // device
+        int dev = 0;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+            throw fail(SIM_EDEVICE, "no HIP device available");
+        HIPCHK(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            throw fail(SIM_EDEVICE, "device %s is not gfx950", prop.gcnArchName);
+        s->n_cu = prop.multiProcessorCount;
+        s->max_lds = (int)std::min<size_t>(prop.maxSharedMemoryPerMultiProcessor, 160 * 1024);
+        if (s->max_lds < (int)prop.sharedMemPerBlock) s->max_lds = (int)prop.sharedMemPerBlock;
+        if (set_epoch_lds_limit(s->max_lds) != hipSuccess) {
+            (void)hipGetLastError();
+            s->max_lds = (int)prop.sharedMemPerBlock;
+        }
+        int clk_khz = 0;
+        if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+            clk_khz > 0)
+            s->tick_ns = 1e6 / (double)clk_khz;
+        if (params->hip_stream) {
+            s->stream = (hipStream_t)params->hip_stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+            s->own_stream = true;
+        }
+        HIPCHK(hipEventCreate(&s->ev0));
+        HIPCHK(hipEventCreate(&s->ev1));
+        s->d_epoch.alloc(1);
+        compute_cost(s);
+        Variant v;
+        v.threads = params->threads ? params->threads : 256;
+        v.pack_comps = params->pack_comps ? params->pack_comps : 1024;
+        v.lds_limit = params->lds_comps
+                          ? (int)std::min<int64_t>(s->max_lds,
+                                                   state_bytes(s, params->lds_comps, params->lds_comps / 4 + 16, 64))
+                          : std::min(64 * 1024, s->max_lds);
+        v.sched = params->sched == SIM_SCHED_DISPATCH ? SIM_SCHED_DISPATCH : SIM_SCHED_PERSISTENT;
+        if (params->autotune)
+            autotune(s, v);
+        else
+            apply_variant(s, v);
+        *out = s;
+        return SIM_OK;
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        if (s) sim_destroy(s);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_create_error = "host allocation failed";
+        if (s) sim_destroy(s);
+        return SIM_ENOMEM;
+    }
+}
+
+int sim_step(sim_t *s, int64_t n_steps) {
+    if (!s) return SIM_EINVAL;
+    if (n_steps < 0) {
+        s->err = "n_steps must be >= 0";
+        return SIM_EINVAL;
+    }
+    try {
+        run_steps(s, n_steps);
+        return SIM_OK;
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
+}
+
+int64_t sim_time_steps(const sim_t *s) { return s ? s->step : -1; }
+
+static int read_comp(sim_t *s, const char *src, int64_t cap, int elem, double *out) {
+    if (!s || !out) return SIM_EINVAL;
+    if (cap < s->C) {
+        s->err = "capacity smaller than the compartment count";
+        return SIM_EINVAL;
+    }
+    try {
+        std::vector<char> host((size_t)s->C * elem);
+        HIPCHK(hipMemcpy(host.data(), src, host.size(), hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < s->C; ++c) {
+            double v;
+            if (elem == 8)
+                std::memcpy(&v, host.data() + c * 8, 8);
+            else {
+                float f;
+                std::memcpy(&f, host.data() + c * 4, 4);
+                v = f;
+            }
+            out[s->comp_perm[c]] = v;
+        }
+        return SIM_OK;
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
+}
+
+int sim_read_voltages(sim_t *s, double *out, int64_t cap) {
+    return s ? read_comp(s, (const char *)s->d_V.p, cap, 8, out) : SIM_EINVAL;
+}
+
+int sim_read_gates(sim_t *s, double *m, double *h, double *n, int64_t cap) {
+    if (!s) return SIM_EINVAL;
+    int rc = read_comp(s, s->d_gm.p, cap, s->tsize, m);
+    if (rc == SIM_OK) rc = read_comp(s, s->d_gh.p, cap, s->tsize, h);
+    if (rc == SIM_OK) rc = read_comp(s, s->d_gn.p, cap, s->tsize, n);
+    return rc;
+}
+
+int sim_read_conductances(sim_t *s, double *out, int64_t cap) {
+    if (!s || !out) return SIM_EINVAL;
+    if (cap < s->S) {
+        s->err = "capacity smaller than the synapse count";
+        return SIM_EINVAL;
+    }
+    try {
+        std::vector<char> host((size_t)s->S * s->tsize);
+        if (s->S) HIPCHK(hipMemcpy(host.data(), s->d_sg.p, host.size(), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < s->S; ++k) {
+            double v;
+            if (s->tsize == 8)
+                std::memcpy(&v, host.data() + k * 8, 8);
+            else {
+                float f;
+                std::memcpy(&f, host.data() + k * 4, 4);
+                v = f;
+            }
+            out[s->syn_perm[k]] = v;
+        }
+        return SIM_OK;
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
+}
+
+int sim_spikes(sim_t *s, sim_spike_t *out, int64_t cap, int64_t *n_total) {
+    if (!s) return SIM_EINVAL;
+    try {
+        const int64_t ne = (s->step + s->E - 1) / s->E;
+        std::vector<uint64_t> h((size_t)ne * s->N);
+        if (ne) HIPCHK(hipMemcpy(h.data(), s->d_hist.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost));
+        int64_t total = 0;
+        for (uint64_t w : h) total += __builtin_popcountll(w);
+        if (n_total) *n_total = total;
+        if (!out) return SIM_OK;  // count query
+        if (cap < total) {
+            s->err = "spike buffer too small";
+            return SIM_EINVAL;
+        }
+        int64_t k = 0;
+        for (int64_t e = 0; e < ne; ++e)
+            for (int t = 0; t < s->E; ++t)
+                for (int32_t j = 0; j < s->N; ++j)
+                    if ((h[(size_t)e * s->N + j] >> t) & 1ull) {
+                        out[k].neuron = j;
+                        out[k].step = (int32_t)(e * s->E + t + 1);
+                        ++k;
+                    }
+        return SIM_OK;
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
+}
+
+int sim_neuron_timings(sim_t *s, double *out, int64_t cap, int32_t reset) {
+    if (!s || !out || cap < s->N) return SIM_EINVAL;
+    try {
+        std::vector<uint64_t> t(s->packs.size());
+        HIPCHK(hipMemcpy(t.data(), s->d_ptime.p, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost));
+        for (int32_t j = 0; j < s->N; ++j) {
+            const int p = s->pack_of_neuron[j];
+            const double share = (double)(s->off[j + 1] - s->off[j]) / (double)s->packs[p].ncomp;
+            out[j] = (double)t[p] * s->tick_ns * share;
+        }
+        if (reset) HIPCHK(hipMemset(s->d_ptime.p, 0, sizeof(uint64_t) * t.size()));
+        return SIM_OK;
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
+}
+
+int sim_features(sim_t *s, float *out, int64_t cap) {
+    if (!s || !out || cap < (int64_t)s->N * kFeat) return SIM_EINVAL;
+    std::memcpy(out, s->feat.data(), sizeof(float) * s->feat.size());
+    return SIM_OK;
+}
+
+int sim_set_kernel_timing(sim_t *s, int32_t on) {
+    if (!s) return SIM_EINVAL;
+    s->kt_on = on != 0;
+    s->kt_ms = 0;
+    s->kt_launches = 0;
+    return SIM_OK;
+}
+
+int sim_kernel_time(sim_t *s, double *ms, int64_t *launches) {
+    if (!s) return SIM_EINVAL;
+    if (ms) *ms = s->kt_ms;
+    if (launches) *launches = s->kt_launches;
+    return SIM_OK;
+}
+
+const char *sim_config_string(const sim_t *s) { return s ? s->config.c_str() : ""; }
+
+void sim_destroy(sim_t *s) {
+    if (!s) return;
+    destroy_graphs(s);
+    auto fr = [](auto &b) { b.free_(); };
+    fr(s->d_packs); fr(s->d_wg_off); fr(s->d_wg_list); fr(s->d_spre); fr(s->d_sdelay);
+    fr(s->d_nid); fr(s->d_ndet); fr(s->d_lvl); fr(s->d_lparent); fr(s->d_V); fr(s->d_cdt);
+    fr(s->d_G); fr(s->d_e); fr(s->d_dc); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
+    fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
+    fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
+    fr(s->d_sseg); fr(s->d_chl); fr(s->d_sched); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
+    fr(s->d_hist); fr(s->d_ptime);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+const char *sim_last_error(const sim_t *s) { return s ? s->err.c_str() : g_create_error.c_str(); }
+
+// ---- cost model -------------------------------------------------------------
+int64_t sim_mlp_nparams(void) { return kMlpParams; }
+
+int sim_mlp_init(float *p, const float *x, const float *y, int64_t n, uint64_t seed) {
+    if (!p || !x || !y || n < 2) {
+        g_create_error = "sim_mlp_init: need params, x, y and n >= 2";
+        return SIM_EINVAL;
+    }
+    const int F = kFeat, H1 = kH1, H2 = kH2;
+    std::memset(p, 0, sizeof(float) * kMlpParams);
+    // standardisation of log(1+x) and of the targets
+    for (int i = 0; i < F; ++i) {
+        double m = 0, v = 0;
+        for (int64_t s = 0; s < n; ++s) m += std::log1p((double)x[s * F + i]);
+        m /= n;
+        for (int64_t s = 0; s < n; ++s) {
+            const double d = std::log1p((double)x[s * F + i]) - m;
+            v += d * d;
+        }
+        v = std::sqrt(v / n);
+        p[i] = (float)m;
+        p[F + i] = (float)(v > 1e-6 ? v : 1.0);
+    }
+    double ym = 0, yv = 0;
+    for (int64_t s = 0; s < n; ++s) ym += y[s];
+    ym /= n;
+    for (int64_t s = 0; s < n; ++s) yv += (y[s] - ym) * (y[s] - ym);
+    yv = std::sqrt(yv / n);
+    const int64_t OW1 = 2 * F, OB1 = OW1 + H1 * F, OW2 = OB1 + H1, OB2 = OW2 + H2 * H1,
+                  OW3 = OB2 + H2, OB3 = OW3 + H2;
+    p[OB3 + 1] = (float)ym;
+    p[OB3 + 2] = (float)(yv > 1e-6 ? yv : 1.0);
+    // He-uniform weights from a 64-bit linear congruential stream
+    uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
+    auto uni = [&]() {
+        st = st * 6364136223846793005ull + 1442695040888963407ull;
+        return (double)(st >> 11) * (1.0 / 9007199254740992.0);
+    };
+    auto fill = [&](int64_t off, int64_t count, int fan_in) {
+        const double a = std::sqrt(6.0 / fan_in);
+        for (int64_t i = 0; i < count; ++i) p[off + i] = (float)((2 * uni() - 1) * a);
+    };
+    fill(OW1, (int64_t)H1 * F, F);
+    fill(OW2, (int64_t)H2 * H1, H1);
+    fill(OW3, H2, H2);
+    return SIM_OK;
+}
+
+int sim_mlp_forward(const float *p, const float *x, int64_t n, float *out) {
+    if (!p || (!x && n) || (!out && n) || n < 0) return SIM_EINVAL;
+    hipError_t e = mlp_forward(p, x, n, out);
+    if (e != hipSuccess) {
+        g_create_error = hipGetErrorString(e);
+        return SIM_EDEVICE;
+    }
+    return SIM_OK;
+}
+
+int sim_mlp_loss_grad(const float *p, const float *x, const float *y, int64_t n, float *loss,
+                      float *grad) {
+    if (!p || !x || !y || !loss || !grad || n < 1) return SIM_EINVAL;
+    hipError_t e = mlp_loss_grad(p, x, y, n, loss, grad);
+    if (e != hipSuccess) {
+        g_create_error = hipGetErrorString(e);
+        return SIM_EDEVICE;
+    }
+    return SIM_OK;
+}
+
+int sim_mlp_train(float *p, const float *x, const float *y, int64_t n, int32_t epochs, float lr,
+                  float *final_loss) {
+    if (!p || !x || !y || n < 1 || epochs < 0 || !(lr > 0)) return SIM_EINVAL;
+    hipError_t e = mlp_train(p, x, y, n, epochs, lr, final_loss);
+    if (e != hipSuccess) {
+        g_create_error = hipGetErrorString(e);
+        return SIM_EDEVICE;
+    }
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Internal layout shared by the host side of the library and its kernels.
+//
+// Device memory holds every neuron in *packed* order: neurons are grouped
+// into packs (one pack = the unit a workgroup advances through an epoch), and
+// a pack's compartments are contiguous (structure-of-arrays, one array per
+// quantity, so consecutive threads touch consecutive addresses). Inside a
+// neuron the compartments keep their input (Hines) order, parent(i) < i.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmh {
+
+// Topology word of a compartment (pack-local indices, < 32767):
+//   bits  0..14  parent compartment, or the neuron's index within the pack
+//                when the compartment is a root
+//   bit   15     Hodgkin-Huxley channels (else passive)
+//   bits 16..30  branch id when the compartment ends a branch (kNone when its
+//                only child is the next compartment)
+//   bit   31     root of a neuron
+constexpr uint32_t kNone = 0x7FFF;
+__host__ __device__ inline uint32_t topo_parent(uint32_t t) { return t & 0x7FFFu; }
+__host__ __device__ inline bool topo_hh(uint32_t t) { return (t >> 15) & 1u; }
+__host__ __device__ inline uint32_t topo_branch(uint32_t t) { return (t >> 16) & 0x7FFFu; }
+__host__ __device__ inline bool topo_root(uint32_t t) { return (t >> 31) & 1u; }
+__host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh,
+                                              uint32_t branch, bool root) {
+    return (parent_or_neuron & 0x7FFFu) | (hh ? 0x8000u : 0u) |
+           ((branch & 0x7FFFu) << 16) | (root ? 0x80000000u : 0u);
+}
+
+// A branch: a maximal run b0..b1 of consecutive compartments where each one
+// is the only child of the previous. Its children (branches whose base hangs
+// off b1) are listed by base compartment, ascending, at child list entries
+// child0 .. child0+nchild-1.
+struct Branch {
+    uint16_t b0, b1, child0, nchild;
+};
+
+struct PackDesc {
+    int64_t comp0;   // first compartment (packed index)
+    int64_t syn0;    // first synapse (packed index)
+    int32_t ncomp, nsyn;
+    int32_t neur0, nneur;  // packed neuron range
+    int32_t br0, nbr;      // branch table range
+    int32_t ch0;           // child list offset
+    int32_t lv0;           // level offsets: nbw+1 backward then nfw+1 forward
+    int32_t nbw, nfw;      // number of height / depth levels
+    int32_t sc0;           // schedule: nbr ids by height, then nbr by depth
+    int32_t global_mem;    // 0: state in LDS; k > 0: state in global scratch slice k-1
+};
+
+// Everything the epoch kernel reads or writes. T is the gating precision.
+struct EpochArgs {
+    const PackDesc *packs;
+    const int32_t *wg_off;   // [n_wg+1] ranges into wg_list
+    const int32_t *wg_list;  // pack ids in execution order
+    // per compartment (packed)
+    double *V;
+    void *gm, *gh, *gn;
+    const uint32_t *topo;
+    const double *cdt;  // C/dt (uS)
+    const double *G;    // coupling to parent (uS), 0 at roots
+    const double *e;    // off-diagonal -theta*G
+    const double *dc;   // constant part of the diagonal
+    const void *af;     // area factor (T)
+    // per synapse (packed: by pack, target compartment, synapse id)
+    void *sg;                 // conductance (T)
+    const void *sw;           // weight (T)
+    const int32_t *spre;      // presynaptic neuron (input id)
+    const int32_t *sdelay;
+    const uint16_t *scomp;    // pack-local target compartment
+    const uint16_t *sseg;     // run length of equal targets at a run start, else 0
+    // per neuron (packed)
+    const int32_t *nid;       // input id
+    const int32_t *ndet;      // pack-local detector compartment
+    const void *niext;        // injected current (T)
+    // per pack tables
+    const Branch *br;
+    const uint16_t *chl;
+    const int32_t *lvl;
+    const uint16_t *sched;
+    // spike history: hist[epoch * n_neurons + input id] = bit t set when the
+    // neuron spiked at step epoch*E + t + 1
+    uint64_t *hist;
+    int32_t n_neurons;
+    int32_t E;
+    const int64_t *epoch_ptr;  // when non-null, the epoch index is read here
+    int64_t epoch;
+    int32_t t0, t1;            // steps [t0, t1) of the epoch
+    // scratch for packs too large for LDS: slice k-1 of scratch_stride bytes
+    char *scratch;
+    int64_t scratch_stride;
+    // constants
+    double omt;        // 1 - theta
+    double v_thresh;
+    double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
+    // timing
+    uint64_t *pack_time;  // accumulated ns per pack, or null
+};
+
+// Bytes of per-pack state for a pack of n compartments, s synapses and k
+// neurons in precision T (must match the carve-up in the kernel).
+template <typename T>
+__host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_t k) {
+    int64_t b = 3 * 8 * n;                 // V, R, D
+    b += 8 * s + 8 * k + 8 * k;            // synapse masks, spike masks, V_det
+    b += ((int64_t)sizeof(T) * (3 * n + s) + 15) / 16 * 16;  // gates, g
+    return (b + 255) / 256 * 256;
+}
+
+struct SetupArgs {
+    int32_t n_neurons;          // packed neuron count
+    const int64_t *ncomp0;      // [n+1] packed compartment offsets per neuron
+    const int32_t *lparent;     // neuron-local parent per compartment
+    const double *length, *diam;
+    double cm, ra, dt, theta, v_init;
+    double *cdt, *G, *e, *dc, *V;
+    void *af, *gm, *gh, *gn;
+    double *q_out;              // exp(-dt/tau)
+    double tau;
+};
+
+// Launchers (kernels.hip).
+hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s);
+hipError_t launch_epoch(const EpochArgs &a, int precision, int n_wg, int threads,
+                        size_t lds_bytes, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_advance(int64_t *epoch, hipStream_t s);
+hipError_t launch_decay_weights_convert(const double *w, void *out, int64_t n,
+                                        int precision, hipStream_t s);
+hipError_t set_epoch_lds_limit(int bytes);
+
+// MLP (mlp.hip).
+constexpr int kFeat = 16, kH1 = 64, kH2 = 64;
+constexpr int64_t kMlpParams = 16 + 16 + kH1 * kFeat + kH1 + kH2 * kH1 + kH2 + kH2 + 1 + 2;
+
+}  // namespace mmh

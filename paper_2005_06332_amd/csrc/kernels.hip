@@ -1,0 +1,531 @@
+// Epoch kernel and setup kernel of the multi-morphology simulator (gfx950).
+//
+// One workgroup advances one pack of neurons through the steps of an epoch
+// (E <= the smallest synaptic delay, so no spike produced inside the epoch
+// can reach a neuron before the epoch ends; Section 2 of the paper, two-level
+// time stepping). While it does so the pack's voltages, gates, conductances
+// and the per-step matrix (diagonal D and right-hand side R) stay in LDS (or,
+// for packs too large for LDS, in a private slice of global scratch that
+// stays resident in L2); only the time-invariant coefficients are re-read.
+//
+// Per step and pack, in the order of the paper's update (Section 2):
+//   A  synaptic delivery from the spike history, per-compartment conductance
+//   B  membrane conductance g and source J per compartment (HH gates of step
+//      n), assembly of Eq. 2: D_i = C_i/dt + theta*sum G + g_i,
+//      R_i = C_i V_i/dt + J_i + (1-theta) * axial current
+//   C  backward sweep of Algorithm 1, one lane per branch, branches grouped
+//      by height so that every child is finished before its parent
+//   D  forward sweep of Algorithm 1, branches grouped by depth
+//   E  gates at V^{n+1} (exponential Euler); threshold-crossing detection
+// Every floating-point operation is performed in the order of Algorithm 1 as
+// written (children of a node eliminated in descending index order), with
+// no contraction, so the result does not depend on how neurons are packed.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace mmh {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Elementary functions. exp: Cody & Waite argument reduction x = k ln2 + r
+// with ln2 split into a high part with trailing zero bits (k*hi exact) and a
+// low part, then the Taylor polynomial of e^r (degree 13 in double, 7 in
+// float) by Horner with fused multiply-adds, then scaling by 2^k through the
+// exponent field.
+// ---------------------------------------------------------------------------
+constexpr double kLn2HiD = 0x1.62e42feep-1;
+constexpr double kLn2LoD = 0x1.a39ef35793c76p-33;
+constexpr double kInvLn2D = 0x1.71547652b82fep+0;
+constexpr float kLn2HiF = 0x1.62e4p-1f;
+constexpr float kLn2LoF = 0x1.7f7d1cp-20f;
+constexpr float kInvLn2F = 0x1.715476p+0f;
+
+__device__ __forceinline__ double dexp(double x) {
+    if (x != x) return x;
+    if (x > 709.0) x = 709.0;
+    if (x < -708.0) x = -708.0;
+    const double k = __builtin_rint(x * kInvLn2D);
+    double r = __builtin_fma(-k, kLn2HiD, x);
+    r = __builtin_fma(-k, kLn2LoD, r);
+    double p = 0x1.6124613a86d09p-33;            // 1/13!
+    p = __builtin_fma(p, r, 0x1.1eed8eff8d898p-29);  // 1/12!
+    p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26);  // 1/11!
+    p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22);  // 1/10!
+    p = __builtin_fma(p, r, 0x1.71de3a556c734p-19);  // 1/9!
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16);  // 1/8!
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13);  // 1/7!
+    p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10);  // 1/6!
+    p = __builtin_fma(p, r, 0x1.1111111111111p-7);   // 1/5!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-5);   // 1/4!
+    p = __builtin_fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+    p = __builtin_fma(p, r, 0x1p-1);                 // 1/2!
+    p = __builtin_fma(p, r, 1.0);                    // 1/1!
+    p = __builtin_fma(p, r, 1.0);                    // 1/0!
+    const long long e = (long long)k + 1023;
+    return p * __longlong_as_double(e << 52);
+}
+
+__device__ __forceinline__ float fexp(float x) {
+    if (x != x) return x;
+    if (x > 88.0f) x = 88.0f;
+    if (x < -87.0f) x = -87.0f;
+    const float k = __builtin_rintf(x * kInvLn2F);
+    float r = __builtin_fmaf(-k, kLn2HiF, x);
+    r = __builtin_fmaf(-k, kLn2LoF, r);
+    float p = 0x1.a01a02p-13f;                  // 1/7!
+    p = __builtin_fmaf(p, r, 0x1.6c16c2p-10f);  // 1/6!
+    p = __builtin_fmaf(p, r, 0x1.111112p-7f);   // 1/5!
+    p = __builtin_fmaf(p, r, 0x1.555556p-5f);   // 1/4!
+    p = __builtin_fmaf(p, r, 0x1.555556p-3f);   // 1/3!
+    p = __builtin_fmaf(p, r, 0x1p-1f);          // 1/2!
+    p = __builtin_fmaf(p, r, 1.0f);             // 1/1!
+    p = __builtin_fmaf(p, r, 1.0f);             // 1/0!
+    const int e = (int)k + 127;
+    return p * __int_as_float(e << 23);
+}
+
+// u / (e^u - 1): Bernoulli series B_2k/(2k)! u^2k near 0, the quotient elsewhere.
+__device__ __forceinline__ double dexprelr(double u) {
+    if (__builtin_fabs(u) < 0.5) {
+        const double w = u * u;
+        double c = -0x1.7da4e1f79955cp-42;
+        c = __builtin_fma(c, w, 0x1.d6db2c4e09162p-37);
+        c = __builtin_fma(c, w, -0x1.22805d644267fp-31);
+        c = __builtin_fma(c, w, 0x1.66a8f2bf70ebep-26);
+        c = __builtin_fma(c, w, -0x1.bbd779334ef0bp-21);
+        c = __builtin_fma(c, w, 0x1.1566abc011567p-15);
+        c = __builtin_fma(c, w, -0x1.6c16c16c16c17p-10);
+        c = __builtin_fma(c, w, 0x1.5555555555555p-4);
+        return __builtin_fma(c, w, __builtin_fma(-0.5, u, 1.0));
+    }
+    return u / (dexp(u) - 1.0);
+}
+
+__device__ __forceinline__ float fexprelr(float u) {
+    if (__builtin_fabsf(u) < 0.5f) {
+        const float w = u * u;
+        float c = -0x1.bbd77ap-21f;
+        c = __builtin_fmaf(c, w, 0x1.1566acp-15f);
+        c = __builtin_fmaf(c, w, -0x1.6c16c2p-10f);
+        c = __builtin_fmaf(c, w, 0x1.555556p-4f);
+        return __builtin_fmaf(c, w, __builtin_fmaf(-0.5f, u, 1.0f));
+    }
+    return u / (fexp(u) - 1.0f);
+}
+
+template <typename T> struct Fn;
+template <> struct Fn<double> {
+    static __device__ __forceinline__ double ex(double x) { return dexp(x); }
+    static __device__ __forceinline__ double exr(double x) { return dexprelr(x); }
+};
+template <> struct Fn<float> {
+    static __device__ __forceinline__ float ex(float x) { return fexp(x); }
+    static __device__ __forceinline__ float exr(float x) { return fexprelr(x); }
+};
+
+// Hodgkin-Huxley rates (1/ms) at v (mV), modern sign convention.
+template <typename T>
+__device__ __forceinline__ void hh_rates(T v, T &am, T &bm, T &ah, T &bh, T &an, T &bn) {
+    am = Fn<T>::exr(-(v + T(40)) / T(10));
+    bm = T(4) * Fn<T>::ex(-(v + T(65)) / T(18));
+    ah = T(0.07) * Fn<T>::ex(-(v + T(65)) / T(20));
+    bh = T(1) / (Fn<T>::ex(-(v + T(35)) / T(10)) + T(1));
+    an = T(0.1) * Fn<T>::exr(-(v + T(55)) / T(10));
+    bn = T(0.125) * Fn<T>::ex(-(v + T(65)) / T(80));
+}
+
+// Exponential Euler: x <- x_inf + (x - x_inf) exp(-dt (a + b)).
+template <typename T>
+__device__ __forceinline__ T gate_step(T x, T a, T b, T dt) {
+    const T s = a + b;
+    const T xinf = a / s;
+    const T ex = Fn<T>::ex(-dt * s);
+    return xinf + (x - xinf) * ex;
+}
+
+// ---------------------------------------------------------------------------
+// Setup: time-invariant coefficients of every neuron, one thread per neuron,
+// in the order of the compartment index (so each node collects its
+// children's couplings in ascending child order).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_setup(SetupArgs a) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0) *a.q_out = dexp(-a.dt / a.tau);
+    if (j >= a.n_neurons) return;
+    const double PI = 3.14159265358979323846;
+    const int64_t c0 = a.ncomp0[j];
+    const int32_t n = (int32_t)(a.ncomp0[j + 1] - c0);
+    T am, bm, ah, bh, an, bn;
+    hh_rates<T>(T(a.v_init), am, bm, ah, bh, an, bn);
+    const T m0 = am / (am + bm), h0 = ah / (ah + bh), n0 = an / (an + bn);
+    T *af = (T *)a.af, *gm = (T *)a.gm, *gh = (T *)a.gh, *gn = (T *)a.gn;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t c = c0 + i;
+        const double area = PI * a.diam[c] * a.length[c];
+        a.cdt[c] = a.cm * area * 1e-5 / a.dt;
+        af[c] = (T)(area * 1e-2);
+        a.dc[c] = a.cdt[c];
+        a.V[c] = a.v_init;
+        gm[c] = m0;
+        gh[c] = h0;
+        gn[c] = n0;
+    }
+    a.G[c0] = 0.0;
+    a.e[c0] = 0.0;
+    for (int32_t i = 1; i < n; ++i) {
+        const int64_t c = c0 + i;
+        const int64_t pc = c0 + a.lparent[c];
+        const double rh = 2.0 * a.ra * a.length[c] / (PI * a.diam[c] * a.diam[c]) * 1e-2;
+        const double rp = 2.0 * a.ra * a.length[pc] / (PI * a.diam[pc] * a.diam[pc]) * 1e-2;
+        const double G = 1.0 / (rh + rp);
+        const double e = -a.theta * G;
+        a.G[c] = G;
+        a.e[c] = e;
+        a.dc[c] -= e;
+        a.dc[pc] -= e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Epoch kernel.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct State {
+    double *V, *R, *D, *VO;
+    uint64_t *SM, *SP;
+    T *M, *H, *N, *SG;
+};
+
+template <typename T>
+__device__ __forceinline__ State<T> carve(char *base, int n, int s, int k) {
+    State<T> p;
+    double *dp = (double *)base;
+    p.V = dp;
+    p.R = dp + n;
+    p.D = dp + 2 * n;
+    uint64_t *up = (uint64_t *)(dp + 3 * n);
+    p.SM = up;
+    p.SP = up + s;
+    p.VO = (double *)(up + s + k);
+    T *tp = (T *)(p.VO + k);
+    p.M = tp;
+    p.H = tp + n;
+    p.N = tp + 2 * n;
+    p.SG = tp + 3 * n;
+    return p;
+}
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+    return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+// Events of synapse (pre, delay) in the steps epoch*E + t, t in [0, E): bit t
+// set when `pre` spiked at step epoch*E + t - delay (>= 1). Reads only
+// epochs before `epoch` because delay >= E.
+__device__ __forceinline__ uint64_t event_mask(const uint64_t *hist, int32_t N, int32_t E,
+                                               int64_t epoch, int32_t pre, int32_t delay) {
+    const int64_t g0 = epoch * E - delay - 1;  // history bit of t = 0
+    if (g0 + E - 1 < 0) return 0;
+    const int64_t w0 = floor_div(g0, E);
+    const int off = (int)(g0 - w0 * E);
+    const uint64_t lo = (w0 >= 0) ? hist[w0 * N + pre] : 0ull;
+    uint64_t m = lo >> off;
+    if (off > 0) {
+        const uint64_t hi = (w0 + 1 >= 0) ? hist[(w0 + 1) * N + pre] : 0ull;
+        m |= hi << (E - off);
+    }
+    if (E < 64) m &= (1ull << E) - 1ull;
+    return m;
+}
+
+template <typename T, bool kGlobal>
+__device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *base,
+                                         int64_t epoch, int pid) {
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    const int n = pk.ncomp, ns = pk.nsyn, nn = pk.nneur;
+    const int64_t c0 = pk.comp0, s0 = pk.syn0;
+    const State<T> st = carve<T>(base, n, ns, nn);
+    double *__restrict__ V = st.V;
+    double *__restrict__ R = st.R;
+    double *__restrict__ D = st.D;
+    T *__restrict__ M = st.M;
+    T *__restrict__ H = st.H;
+    T *__restrict__ Ng = st.N;
+    T *__restrict__ SG = st.SG;
+
+    const T *gm = (const T *)a.gm, *gh = (const T *)a.gh, *gn = (const T *)a.gn;
+    const T *af = (const T *)a.af;
+    const T *sw = (const T *)a.sw;
+    const T *niext = (const T *)a.niext;
+    const Branch *br = a.br + pk.br0;
+    const uint16_t *chl = a.chl + pk.ch0;
+    const int32_t *lvl = a.lvl + pk.lv0;
+    const uint16_t *sched = a.sched + pk.sc0;
+
+    const T gnabar = (T)a.gnabar, gkbar = (T)a.gkbar, gl = (T)a.gl;
+    const T ena = (T)a.ena, ek = (T)a.ek, el = (T)a.el;
+    const T g_pas = (T)a.g_pas, e_pas = (T)a.e_pas, e_syn = (T)a.e_syn;
+    const T dt = (T)a.dt, q = (T)a.q;
+    const double omt = a.omt, vth = a.v_thresh;
+    const int t0 = a.t0, t1 = a.t1;
+
+    // ---- load state -------------------------------------------------------
+    for (int i = tid; i < n; i += NT) {
+        V[i] = a.V[c0 + i];
+        M[i] = gm[c0 + i];
+        H[i] = gh[c0 + i];
+        Ng[i] = gn[c0 + i];
+        R[i] = 0.0;  // holds the synaptic conductance of compartment i in phase A/B
+    }
+    for (int k = tid; k < ns; k += NT) {
+        SG[k] = ((const T *)a.sg)[s0 + k];
+        st.SM[k] = event_mask(a.hist, a.n_neurons, a.E, epoch, a.spre[s0 + k], a.sdelay[s0 + k]);
+    }
+    for (int k = tid; k < nn; k += NT) {
+        st.VO[k] = a.V[c0 + a.ndet[pk.neur0 + k]];
+        st.SP[k] = 0ull;
+    }
+    __syncthreads();
+
+    for (int t = t0; t < t1; ++t) {
+        // ---- A: delivery and per-compartment synaptic conductance ----------
+        for (int k = tid; k < ns; k += NT) {
+            const int L = a.sseg[s0 + k];
+            if (L == 0) continue;
+            T sum = T(0);
+            for (int j = k; j < k + L; ++j) {
+                T g = SG[j];
+                if (t > t0) g = q * g;
+                if ((st.SM[j] >> t) & 1ull) g = g + sw[s0 + j];
+                SG[j] = g;
+                sum = sum + g;
+            }
+            *(T *)&R[a.scomp[s0 + k]] = sum;
+        }
+        __syncthreads();
+
+        // ---- B: membrane terms and assembly --------------------------------
+        for (int i = tid; i < n; i += NT) {
+            const int64_t gc = c0 + i;
+            const uint32_t tp = a.topo[gc];
+            const double v = V[i];
+            const T gs = *(const T *)&R[i];
+            T gion, jion;
+            if (topo_hh(tp)) {
+                const T m = M[i], h = H[i], x = Ng[i];
+                const T gna = gnabar * (((m * m) * m) * h);
+                const T gk = gkbar * (((x * x) * x) * x);
+                gion = (gna + gk) + gl;
+                jion = (gna * ena + gk * ek) + gl * el;
+            } else {
+                gion = g_pas;
+                jion = g_pas * e_pas;
+            }
+            const bool root = topo_root(tp);
+            const T iext = root ? niext[pk.neur0 + topo_parent(tp)] : T(0);
+            const T afv = af[gc];
+            const T gmem = afv * gion + gs;
+            const T J = (afv * jion + gs * e_syn) + iext;
+            double ax = root ? 0.0 : a.G[gc] * (V[topo_parent(tp)] - v);
+            const uint32_t bid = topo_branch(tp);
+            if (bid == kNone) {
+                ax = ax - a.G[gc + 1] * (v - V[i + 1]);
+            } else {
+                const Branch b = br[bid];
+                for (int c = 0; c < b.nchild; ++c) {
+                    const int j = chl[b.child0 + c];
+                    ax = ax - a.G[c0 + j] * (v - V[j]);
+                }
+            }
+            D[i] = a.dc[gc] + (double)gmem;
+            R[i] = (a.cdt[gc] * v + (double)J) + omt * ax;
+        }
+        __syncthreads();
+
+        // ---- C: backward sweep by height -----------------------------------
+        for (int h = 0; h < pk.nbw; ++h) {
+            for (int q2 = lvl[h] + tid; q2 < lvl[h + 1]; q2 += NT) {
+                const Branch b = br[sched[q2]];
+                double dd = D[b.b1], rr = R[b.b1];
+                for (int c = b.nchild - 1; c >= 0; --c) {
+                    const int j = chl[b.child0 + c];
+                    const double ej = a.e[c0 + j];
+                    const double f = ej / D[j];
+                    dd = dd - f * ej;
+                    rr = rr - f * R[j];
+                }
+                for (int i = b.b1; i > b.b0; --i) {
+                    D[i] = dd;
+                    R[i] = rr;
+                    const double ei = a.e[c0 + i];
+                    const double f = ei / dd;
+                    dd = D[i - 1] - f * ei;
+                    rr = R[i - 1] - f * rr;
+                }
+                D[b.b0] = dd;
+                R[b.b0] = rr;
+            }
+            __syncthreads();
+        }
+
+        // ---- D: forward sweep by depth -------------------------------------
+        const int32_t *flv = lvl + pk.nbw + 1;
+        const uint16_t *fsc = sched + pk.nbr;
+        for (int h = 0; h < pk.nfw; ++h) {
+            for (int q2 = flv[h] + tid; q2 < flv[h + 1]; q2 += NT) {
+                const Branch b = br[fsc[q2]];
+                const uint32_t tp = a.topo[c0 + b.b0];
+                double x;
+                if (topo_root(tp))
+                    x = R[b.b0] / D[b.b0];
+                else
+                    x = (R[b.b0] - a.e[c0 + b.b0] * V[topo_parent(tp)]) / D[b.b0];
+                V[b.b0] = x;
+                for (int i = b.b0 + 1; i <= b.b1; ++i) {
+                    x = (R[i] - a.e[c0 + i] * x) / D[i];
+                    V[i] = x;
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- E: gates at V^{n+1}; detection --------------------------------
+        for (int i = tid; i < n; i += NT) {
+            const uint32_t tp = a.topo[c0 + i];
+            if (topo_hh(tp)) {
+                const T v = (T)V[i];
+                T am, bm, ah, bh, an, bn;
+                hh_rates<T>(v, am, bm, ah, bh, an, bn);
+                M[i] = gate_step<T>(M[i], am, bm, dt);
+                H[i] = gate_step<T>(H[i], ah, bh, dt);
+                Ng[i] = gate_step<T>(Ng[i], an, bn, dt);
+            }
+            R[i] = 0.0;
+        }
+        for (int k = tid; k < nn; k += NT) {
+            const double vn = V[a.ndet[pk.neur0 + k]];
+            if (st.VO[k] < vth && vn >= vth) st.SP[k] |= 1ull << t;
+            st.VO[k] = vn;
+        }
+        __syncthreads();
+    }
+
+    // ---- write back -----------------------------------------------------------
+    T *ogm = (T *)a.gm, *ogh = (T *)a.gh, *ogn = (T *)a.gn;
+    for (int i = tid; i < n; i += NT) {
+        a.V[c0 + i] = V[i];
+        ogm[c0 + i] = M[i];
+        ogh[c0 + i] = H[i];
+        ogn[c0 + i] = Ng[i];
+    }
+    if (t1 > t0) {
+        T *osg = (T *)a.sg;
+        for (int k = tid; k < ns; k += NT) osg[s0 + k] = q * SG[k];
+    }
+    for (int k = tid; k < nn; k += NT) {
+        if (st.SP[k]) {
+            uint64_t *w = a.hist + epoch * a.n_neurons + a.nid[pk.neur0 + k];
+            *w = *w | st.SP[k];
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_epoch(EpochArgs a) {
+    extern __shared__ __align__(16) char smem[];
+    const int64_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
+    const int q0 = a.wg_off[blockIdx.x], q1 = a.wg_off[blockIdx.x + 1];
+    for (int q = q0; q < q1; ++q) {
+        const int pid = a.wg_list[q];
+        const PackDesc pk = a.packs[pid];
+        uint64_t tstart = 0;
+        if (a.pack_time && threadIdx.x == 0) tstart = wall_clock64();
+        if (pk.global_mem)
+            run_pack<T, true>(a, pk, a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride,
+                              epoch, pid);
+        else
+            run_pack<T, false>(a, pk, smem, epoch, pid);
+        __syncthreads();
+        if (a.pack_time && threadIdx.x == 0)
+            atomicAdd((unsigned long long *)&a.pack_time[pid],
+                      (unsigned long long)(wall_clock64() - tstart));
+    }
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_advance(int64_t *epoch) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *epoch = *epoch + 1;
+}
+
+template <typename T>
+__global__ void k_convert(const double *w, T *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (T)w[i];
+}
+
+}  // namespace
+
+hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s) {
+    const int nt = 128;
+    const int nb = (a.n_neurons + nt - 1) / nt;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_setup<double>, dim3(nb > 0 ? nb : 1), dim3(nt), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_setup<float>, dim3(nb > 0 ? nb : 1), dim3(nt), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_epoch(const EpochArgs &a, int precision, int n_wg, int threads,
+                        size_t lds_bytes, hipStream_t s) {
+    if (precision == 0)
+        hipLaunchKernelGGL(k_epoch<double>, dim3(n_wg), dim3(threads), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(k_epoch<float>, dim3(n_wg), dim3(threads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t set_epoch_lds_limit(int bytes) {
+    hipError_t e1 = hipFuncSetAttribute((const void *)k_epoch<double>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e2 = hipFuncSetAttribute((const void *)k_epoch<float>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e1 != hipSuccess ? e1 : e2;
+}
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *epoch, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, epoch);
+    return hipGetLastError();
+}
+
+hipError_t launch_decay_weights_convert(const double *w, void *out, int64_t n, int precision,
+                                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_convert<double>, dim3((unsigned)nb), dim3(256), 0, s, w,
+                           (double *)out, n);
+    else
+        hipLaunchKernelGGL(k_convert<float>, dim3((unsigned)nb), dim3(256), 0, s, w,
+                           (float *)out, n);
+    return hipGetLastError();
+}
+
+}  // namespace mmh

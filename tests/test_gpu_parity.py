@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+Both sides receive the same seeded inputs. Floating-point tolerance: 1e-9 mV
+on every voltage (FP64 and FP32-gating modes alike, since both sides
+evaluate the same operations in the same order); spike trains must be
+identical. The tests also report how many voltages differ at all.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2005_06332_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_MV = 1e-9
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2005_06332_amd import sim
+    sim.lib()
+    return sim
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare(tag, v_gpu, v_ref, s_gpu, s_ref):
+    d = np.abs(v_gpu - v_ref)
+    nz = int(np.count_nonzero(d))
+    say(f"{tag}: max|dV|={d.max():.3e} mV, differing={nz}/{d.size}, "
+        f"spikes gpu={len(s_gpu)} ref={len(s_ref)}")
+    assert np.all(np.isfinite(v_gpu))
+    assert d.max() <= TOL_MV, tag
+    assert s_gpu.shape == s_ref.shape and np.array_equal(s_gpu, s_ref), tag
+
+
+def run_pair(S, orc, prob, steps, precision, chunks=None, **kw):
+    say(f"case {prob['name']} N={prob['n_comp'].shape[0]} steps={steps} prec={precision} {kw}")
+    ref = orc.Sim(prob, max_steps=steps, precision=precision)
+    ref.step(steps)
+    with S.Simulation(prob, precision=precision, **kw) as g:
+        say("  config:", g.config)
+        if chunks:
+            for c in chunks:
+                g.step(c)
+        else:
+            g.step(steps)
+        assert g.step_count == steps
+        out = (g.voltages(), g.spikes(), g.gates(), g.conductances())
+    vr, sr = ref.voltages(), ref.spikes()
+    mr, hr, nr = ref.gates()
+    gr = ref.g()
+    ref.close()
+    return out, (vr, sr, (mr, hr, nr), gr)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_matches_oracle(S, orc, precision):
+    prob = W.config1()
+    (v, s, gates, g), (vr, sr, gr_, gref) = run_pair(S, orc, prob, 400, precision)
+    compare(f"cfg1 prec={precision}", v, vr, s, sr)
+    for a, b in zip(gates, gr_):
+        assert np.max(np.abs(a - b)) <= 1e-12
+    assert np.max(np.abs(g - gref)) <= 1e-12
+    assert len(sr) > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("packing,sched,pack_comps,lds", [
+    (0, 0, 0, 0),        # plain, one workgroup per pack
+    (1, 1, 0, 0),        # count + persistent LPT
+    (1, 2, 300, 0),      # count, dispatch, several neurons per pack
+    (1, 1, 64, 0),       # one neuron per pack
+    (1, 1, 600, 120),    # big packs in global scratch
+])
+def test_multimorphology_matches_oracle(S, orc, precision, packing, sched, pack_comps, lds):
+    prob = W.mini(n_steps=240)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 240, precision, packing=packing,
+                                            sched=sched, pack_comps=pack_comps, lds_comps=lds)
+    compare(f"mini prec={precision} pk={packing} sc={sched} pc={pack_comps} lds={lds}",
+            v, vr, s, sr)
+    assert len(sr) > 0
+
+
+def test_partial_epochs_and_graph_replay_match(S, orc):
+    prob = W.mini(seed=13, n_steps=300, delay_lo=40, delay_hi=90)
+    chunks = [7, 33, 1, 79, 80, 100]
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 300, 1, chunks=chunks)
+    compare("mini partial epochs", v, vr, s, sr)
+
+
+def test_variable_delays_match(S, orc):
+    prob = W.mini(seed=17, n_steps=400, delay_lo=40, delay_hi=200, n_neurons=64)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 400, 1)
+    compare("mini delays 40..200", v, vr, s, sr)
+
+
+def test_epoch_shorter_than_delay_matches(S, orc):
+    prob = W.mini(seed=19, n_steps=200, n_neurons=40)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 200, 0, epoch_steps=13)
+    compare("mini E=13", v, vr, s, sr)
+
+
+def test_single_compartment_and_tiny_neurons(S, orc):
+    rng = np.random.default_rng(3)
+    prob = W.mini(seed=23, n_neurons=30, n_steps=160)
+    # replace three neurons by single compartments (the n = 1 special case)
+    sizes = prob["n_comp"].copy()
+    keep = np.arange(sizes.shape[0])
+    sub = W.subset(prob, keep)
+    for j in (0, 5, 29):
+        a, b = sub["comp_off"][j], sub["comp_off"][j + 1]
+        sub["parent"][a] = -1
+    parts = []
+    off = sub["comp_off"]
+    newoff = [0]
+    for j in range(sizes.shape[0]):
+        n = 1 if j in (0, 5, 29) else int(off[j + 1] - off[j])
+        parts.append(np.arange(off[j], off[j] + n))
+        newoff.append(newoff[-1] + n)
+    idx = np.concatenate(parts)
+    for k in ("parent", "length_um", "diam_um", "mech"):
+        sub[k] = sub[k][idx]
+    sub["comp_off"] = np.array(newoff, np.int64)
+    sub["n_comp"] = np.diff(sub["comp_off"]).astype(np.int32)
+    sub["syn_comp"] = np.minimum(sub["syn_comp"], sub["n_comp"][sub["syn_post"]] - 1)
+    sub["detector"] = np.minimum(sub["detector"], sub["n_comp"] - 1)
+    del rng
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, sub, 160, 1)
+    compare("mini with n=1 neurons", v, vr, s, sr)
+
+
+def test_packing_and_launch_variants_are_bitwise_identical(S):
+    prob = W.mini(seed=29, n_steps=200, n_neurons=96)
+    base = None
+    for kw in (dict(packing=0), dict(packing=1, sched=1), dict(packing=1, sched=2),
+               dict(packing=1, sched=1, threads=64), dict(packing=1, sched=1, threads=512),
+               dict(packing=1, sched=1, pack_comps=2000), dict(packing=1, sched=1, lds_comps=64),
+               dict(packing=1, use_graph=False), dict(packing=1, autotune=True)):
+        with S.Simulation(prob, **kw) as g:
+            g.step(200)
+            out = (g.voltages(), g.spikes())
+            say(kw, g.config)
+        if base is None:
+            base = out
+        else:
+            assert np.array_equal(out[0], base[0]), kw
+            assert np.array_equal(out[1], base[1]), kw
+
+
+def test_validation_errors_do_not_touch_the_device(S):
+    prob = W.config1()
+    bad = dict(prob)
+    bad["syn_delay"] = prob["syn_delay"].copy()
+    bad["syn_delay"][0] = 0
+    with pytest.raises(S.SimError) as e:
+        S.Simulation(bad)
+    assert e.value.code == S.SIM_EINVAL
+    with pytest.raises(S.SimError) as e:
+        S.Simulation(prob, epoch_steps=41)
+    assert e.value.code == S.SIM_EINVAL
