@@ -54,7 +54,7 @@ extern "C" {
 #define SIM_PACK_LEARNED 2  /* cost = MLP prediction (falls back to COUNT
                                when no model is given) */
 
-#define SIM_SCHED_AUTO 0       /* chosen by the autotuner, else PERSISTENT */
+#define SIM_SCHED_AUTO 0       /* chosen by the autotuner, else DISPATCH */
 #define SIM_SCHED_PERSISTENT 1 /* one resident workgroup per slot; static LPT
                                   lists of packs */
 #define SIM_SCHED_DISPATCH 2   /* one workgroup per pack in cost order */
@@ -114,8 +114,9 @@ typedef struct {
                             <= 64 */
     int32_t autotune;    /* 1: time trial epochs over launch variants at
                             create and keep the fastest */
-    int32_t threads;     /* workgroup size 64..1024 (multiple of 64), 0 = 256 */
-    int32_t pack_comps;  /* target compartments per pack, 0 = 1024 */
+    int32_t threads;     /* workgroup size 64..1024 (multiple of 64; at most 512
+                            in SIM_FP64), 0 = 512 */
+    int32_t pack_comps;  /* target compartments per pack, 0 = 1400 */
     int32_t lds_comps;   /* largest pack kept in LDS; larger packs use global
                             scratch. 0 = derived from the LDS budget */
     int32_t use_graph;   /* 1: replay whole epochs from a captured hipGraph */

@@ -225,7 +225,7 @@ struct sim {
     bool own_stream = false;
     DBuf<PackDesc> d_packs;
     DBuf<int32_t> d_wg_off, d_wg_list, d_spre, d_sdelay, d_nid, d_ndet, d_lvl, d_lparent;
-    DBuf<double> d_V, d_cdt, d_G, d_e, d_dc, d_len, d_diam, d_w64, d_iext64, d_q;
+    DBuf<double> d_V, d_cdt, d_e, d_len, d_diam, d_w64, d_iext64, d_q;
     DBuf<char> d_gm, d_gh, d_gn, d_af, d_sg, d_sw, d_niext, d_scratch;
     DBuf<uint32_t> d_topo;
     DBuf<uint16_t> d_scomp, d_sseg, d_chl, d_sched;
@@ -414,7 +414,8 @@ int64_t state_bytes(const sim_t *s, int64_t n, int64_t ns, int64_t k) {
     return s->tsize == 8 ? pack_state_bytes<double>(n, ns, k) : pack_state_bytes<float>(n, ns, k);
 }
 
-void build_layout(sim_t *s, const Variant &v) {
+void build_layout(sim_t *s, Variant v) {
+    v.threads = std::min(v.threads, s->tsize == 8 ? kMaxThreadsF64 : kMaxThreadsF32);
     s->var = v;
     const int32_t N = s->N;
     // neuron order
@@ -473,6 +474,7 @@ void build_layout(sim_t *s, const Variant &v) {
     int64_t lds_max = 0, scratch = 0;
     std::vector<std::pair<int64_t, int64_t>> segs;  // (local comp, synapse id)
 
+
     for (int p = 0; p < npk; ++p) {
         PackDesc d{};
         d.comp0 = (int64_t)topo.size();
@@ -520,6 +522,8 @@ void build_layout(sim_t *s, const Variant &v) {
                 r.b1 = (uint16_t)(comp_base + t.b1[bb]);
                 r.child0 = (uint16_t)(chl.size() - d.ch0);
                 r.nchild = (uint16_t)(t.child_off[bb + 1] - t.child_off[bb]);
+                r.par = bb == 0 ? kRootPar : (uint16_t)(comp_base + s->parent[b + t.b0[bb]]);
+                r.pad = 0;
                 for (int32_t c = t.child_off[bb]; c < t.child_off[bb + 1]; ++c)
                     chl.push_back((uint16_t)(comp_base + t.b0[t.child[c]]));
                 brs.push_back(r);
@@ -562,30 +566,52 @@ void build_layout(sim_t *s, const Variant &v) {
         d.nfw = maxd + 1;
         const int32_t nbr = d.nbr;
         std::vector<int32_t> cnt(std::max(d.nbw, d.nfw) + 1, 0);
+        // within a level, longest chains first so that the lanes of a wave
+        // finish together
+        auto chain_len = [&](int32_t bb, bool with_children) {
+            const Branch &r = brs[d.br0 + bb];
+            return (int)(r.b1 - r.b0) + (with_children ? (int)r.nchild : 0);
+        };
+        std::vector<int32_t> lev;
         lvl.push_back(0);
         for (int h = 0; h < d.nbw; ++h) {
+            lev.clear();
             for (int32_t bb = 0; bb < nbr; ++bb)
-                if (bh[bb] == h) sched.push_back((uint16_t)bb);
+                if (bh[bb] == h) lev.push_back(bb);
+            std::stable_sort(lev.begin(), lev.end(), [&](int32_t x, int32_t y) {
+                return chain_len(x, true) > chain_len(y, true);
+            });
+            for (int32_t bb : lev) sched.push_back((uint16_t)bb);
             lvl.push_back((int32_t)(sched.size() - d.sc0));
         }
         lvl.push_back(0);
         for (int h = 0; h < d.nfw; ++h) {
+            lev.clear();
             for (int32_t bb = 0; bb < nbr; ++bb)
-                if (bd[bb] == h) sched.push_back((uint16_t)bb);
+                if (bd[bb] == h) lev.push_back(bb);
+            std::stable_sort(lev.begin(), lev.end(), [&](int32_t x, int32_t y) {
+                return chain_len(x, false) > chain_len(y, false);
+            });
+            for (int32_t bb : lev) sched.push_back((uint16_t)bb);
             lvl.push_back((int32_t)(sched.size() - d.sc0 - nbr));
         }
+        d.nch = (int32_t)chl.size() - d.ch0;
+        d.tbytes = (int32_t)pack_table_bytes(d.nbr, d.nch, d.nbw + d.nfw + 2);
         const int64_t bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
-        if (bytes <= v.lds_limit) {
+        if (d.tbytes + bytes <= v.lds_limit) {
             d.global_mem = 0;
-            lds_max = std::max(lds_max, bytes);
+            lds_max = std::max(lds_max, d.tbytes + bytes);
         } else {
             d.global_mem = 1;
+            lds_max = std::max<int64_t>(lds_max, d.tbytes);
             scratch = std::max(scratch, bytes);
         }
+        if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
         s->packs[p] = d;
     }
     ncomp0.push_back((int64_t)topo.size());
     s->lds_bytes = (size_t)std::max<int64_t>(lds_max, 256);
+
     s->scratch_bytes = scratch;
 
     // workgroup lists
@@ -649,9 +675,7 @@ void build_layout(sim_t *s, const Variant &v) {
     const int64_t C = s->C, S = s->S;
     s->d_V.alloc(C);
     s->d_cdt.alloc(C);
-    s->d_G.alloc(C);
     s->d_e.alloc(C);
-    s->d_dc.alloc(C);
     s->d_gm.alloc(C * s->tsize);
     s->d_gh.alloc(C * s->tsize);
     s->d_gn.alloc(C * s->tsize);
@@ -678,9 +702,7 @@ void init_state(sim_t *s) {
     a.theta = s->P.theta;
     a.v_init = s->P.v_init_mV;
     a.cdt = s->d_cdt.p;
-    a.G = s->d_G.p;
     a.e = s->d_e.p;
-    a.dc = s->d_dc.p;
     a.V = s->d_V.p;
     a.af = s->d_af.p;
     a.gm = s->d_gm.p;
@@ -736,9 +758,7 @@ EpochArgs make_args(sim_t *s) {
     a.gn = s->d_gn.p;
     a.topo = s->d_topo.p;
     a.cdt = s->d_cdt.p;
-    a.G = s->d_G.p;
     a.e = s->d_e.p;
-    a.dc = s->d_dc.p;
     a.af = s->d_af.p;
     a.sg = s->d_sg.p;
     a.sw = s->d_sw.p;
@@ -759,6 +779,7 @@ EpochArgs make_args(sim_t *s) {
     a.scratch = s->d_scratch.p;
     a.scratch_stride = 0;
     a.omt = 1.0 - s->P.theta;
+    a.ginv = -1.0 / s->P.theta;
     a.v_thresh = s->P.v_thresh_mV;
     a.gnabar = s->CH.gnabar;
     a.gkbar = s->CH.gkbar;
@@ -806,7 +827,8 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
     a.t0 = t0;
     a.t1 = t1;
     a.scratch_stride = s->scratch_bytes;
-    HIPCHK(launch_epoch(a, s->precision == SIM_FP64 ? 0 : 1, s->n_wg, s->var.threads, s->lds_bytes,
+    HIPCHK(launch_epoch(a, s->precision == SIM_FP64 ? 0 : 1, s->n_wg, s->var.threads,
+                        s->lds_bytes,
                         s->stream));
 }
 
@@ -872,8 +894,8 @@ std::string describe(const sim_t *s) {
     int nglob = 0;
     for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
     snprintf(buf, sizeof buf,
-             "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d wg=%d "
-             "lds_bytes=%zu E=%d precision=%s packing=%s",
+             "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d "
+             "wg=%d lds_bytes=%zu E=%d precision=%s packing=%s",
              s->var.threads, s->var.pack_comps, s->var.lds_limit,
              (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
                                                                                     : "persistent",
@@ -898,17 +920,21 @@ void apply_variant(sim_t *s, const Variant &v) {
 // move neurons between workgroups or memory spaces.
 void autotune(sim_t *s, Variant base) {
     std::vector<Variant> cand;
-    for (int thr : {128, 256})
-        for (int pc : {512, 1024, 2048})
-            for (int lds : {48 * 1024, 96 * 1024})
-                for (int sc : {SIM_SCHED_PERSISTENT, SIM_SCHED_DISPATCH}) {
-                    Variant v = base;
-                    v.threads = thr;
-                    v.pack_comps = pc;
-                    v.lds_limit = std::min(lds, s->max_lds);
-                    v.sched = sc;
-                    cand.push_back(v);
-                }
+    for (int thr : {256, 512})
+        for (int pc : {1024, 1400, 2048})
+            for (int lds : {64 * 1024, 80 * 1024}) {
+                Variant v = base;
+                v.threads = thr;
+                v.pack_comps = pc;
+                v.lds_limit = std::min(lds, s->max_lds);
+                v.sched = SIM_SCHED_DISPATCH;
+                cand.push_back(v);
+            }
+    {
+        Variant v = base;
+        v.sched = SIM_SCHED_PERSISTENT;
+        cand.push_back(v);
+    }
     double best = 1e30;
     Variant bestv = base;
     for (const Variant &v : cand) {
@@ -997,13 +1023,13 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
         s->d_epoch.alloc(1);
         compute_cost(s);
         Variant v;
-        v.threads = params->threads ? params->threads : 256;
-        v.pack_comps = params->pack_comps ? params->pack_comps : 1024;
+        v.threads = params->threads ? params->threads : 512;
+        v.pack_comps = params->pack_comps ? params->pack_comps : 1400;
         v.lds_limit = params->lds_comps
                           ? (int)std::min<int64_t>(s->max_lds,
                                                    state_bytes(s, params->lds_comps, params->lds_comps / 4 + 16, 64))
-                          : std::min(64 * 1024, s->max_lds);
-        v.sched = params->sched == SIM_SCHED_DISPATCH ? SIM_SCHED_DISPATCH : SIM_SCHED_PERSISTENT;
+                          : std::min(72 * 1024, s->max_lds);
+        v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
         if (params->autotune)
             autotune(s, v);
         else
@@ -1181,7 +1207,7 @@ void sim_destroy(sim_t *s) {
     auto fr = [](auto &b) { b.free_(); };
     fr(s->d_packs); fr(s->d_wg_off); fr(s->d_wg_list); fr(s->d_spre); fr(s->d_sdelay);
     fr(s->d_nid); fr(s->d_ndet); fr(s->d_lvl); fr(s->d_lparent); fr(s->d_V); fr(s->d_cdt);
-    fr(s->d_G); fr(s->d_e); fr(s->d_dc); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
+    fr(s->d_e); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
     fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
     fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
     fr(s->d_sseg); fr(s->d_chl); fr(s->d_sched); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);

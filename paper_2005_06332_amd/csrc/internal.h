@@ -32,9 +32,11 @@ __host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh
 // A branch: a maximal run b0..b1 of consecutive compartments where each one
 // is the only child of the previous. Its children (branches whose base hangs
 // off b1) are listed by base compartment, ascending, at child list entries
-// child0 .. child0+nchild-1.
+// child0 .. child0+nchild-1. par is the parent compartment of b0, or kRootPar
+// when b0 is the root of its neuron.
+constexpr uint16_t kRootPar = 0xFFFF;
 struct Branch {
-    uint16_t b0, b1, child0, nchild;
+    uint16_t b0, b1, child0, nchild, par, pad;
 };
 
 struct PackDesc {
@@ -48,6 +50,8 @@ struct PackDesc {
     int32_t nbw, nfw;      // number of height / depth levels
     int32_t sc0;           // schedule: nbr ids by height, then nbr by depth
     int32_t global_mem;    // 0: state in LDS; k > 0: state in global scratch slice k-1
+    int32_t nch;           // child list entries
+    int32_t tbytes;        // bytes of staged tables (always in LDS)
 };
 
 // Everything the epoch kernel reads or writes. T is the gating precision.
@@ -60,9 +64,7 @@ struct EpochArgs {
     void *gm, *gh, *gn;
     const uint32_t *topo;
     const double *cdt;  // C/dt (uS)
-    const double *G;    // coupling to parent (uS), 0 at roots
-    const double *e;    // off-diagonal -theta*G
-    const double *dc;   // constant part of the diagonal
+    const double *e;    // off-diagonal -theta*G (G = coupling to parent, uS), 0 at roots
     const void *af;     // area factor (T)
     // per synapse (packed: by pack, target compartment, synapse id)
     void *sg;                 // conductance (T)
@@ -93,6 +95,7 @@ struct EpochArgs {
     int64_t scratch_stride;
     // constants
     double omt;        // 1 - theta
+    double ginv;       // -1/theta (exact: theta is 1/2 or 1)
     double v_thresh;
     double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
     // timing
@@ -103,10 +106,18 @@ struct EpochArgs {
 // neurons in precision T (must match the carve-up in the kernel).
 template <typename T>
 __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_t k) {
-    int64_t b = 3 * 8 * n;                 // V, R, D
+    int64_t b = 4 * 8 * n;                 // V, R, D, off-diagonal
     b += 8 * s + 8 * k + 8 * k;            // synapse masks, spike masks, V_det
-    b += ((int64_t)sizeof(T) * (3 * n + s) + 15) / 16 * 16;  // gates, g
-    return (b + 255) / 256 * 256;
+    b += ((int64_t)sizeof(T) * s + 15) / 16 * 16;  // synaptic conductances
+    return b;
+}
+// Bytes of the pack's topology tables staged next to the state: branch
+// records, child list, schedule (two orders) and level offsets.
+__host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev) {
+    int64_t b = (int64_t)sizeof(Branch) * nbr;
+    b += 2 * nch + 2 * 2 * nbr;
+    b = (b + 3) / 4 * 4 + 4 * nlev;
+    return (b + 15) / 16 * 16;
 }
 
 struct SetupArgs {
@@ -115,7 +126,7 @@ struct SetupArgs {
     const int32_t *lparent;     // neuron-local parent per compartment
     const double *length, *diam;
     double cm, ra, dt, theta, v_init;
-    double *cdt, *G, *e, *dc, *V;
+    double *cdt, *e, *V;
     void *af, *gm, *gh, *gn;
     double *q_out;              // exp(-dt/tau)
     double tau;
@@ -130,6 +141,10 @@ hipError_t launch_advance(int64_t *epoch, hipStream_t s);
 hipError_t launch_decay_weights_convert(const double *w, void *out, int64_t n,
                                         int precision, hipStream_t s);
 hipError_t set_epoch_lds_limit(int bytes);
+// Largest epoch-kernel workgroup (launch bounds): double precision needs
+// more registers per lane.
+constexpr int kMaxThreadsF32 = 1024;
+constexpr int kMaxThreadsF64 = 512;
 
 // MLP (mlp.hip).
 constexpr int kFeat = 16, kH1 = 64, kH2 = 64;

@@ -25,6 +25,25 @@
 #include "internal.h"
 
 namespace mmh {
+
+#ifdef MMH_PHASE_PROFILE
+// Optional per-phase wall-clock accounting (workgroup time in each phase of
+// the step loop), compiled only into profiling builds.
+__device__ unsigned long long g_phase_ticks[8];
+#define MMH_PHASE(k)                                                             \
+    do {                                                                         \
+        if (threadIdx.x == 0) {                                                  \
+            const uint64_t now_ = wall_clock64();                                \
+            atomicAdd(&g_phase_ticks[k], (unsigned long long)(now_ - ph_t_));    \
+            ph_t_ = now_;                                                        \
+        }                                                                        \
+    } while (0)
+#else
+#define MMH_PHASE(k) \
+    do {             \
+    } while (0)
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -145,9 +164,9 @@ __device__ __forceinline__ T gate_step(T x, T a, T b, T dt) {
 }
 
 // ---------------------------------------------------------------------------
-// Setup: time-invariant coefficients of every neuron, one thread per neuron,
-// in the order of the compartment index (so each node collects its
-// children's couplings in ascending child order).
+// Setup: time-invariant coefficients of every neuron (capacitance over dt,
+// area factor, off-diagonal -theta G with G the coupling through the two
+// half-compartment resistances) and the initial state. One thread per neuron.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void k_setup(SetupArgs a) {
@@ -166,13 +185,11 @@ __global__ void k_setup(SetupArgs a) {
         const double area = PI * a.diam[c] * a.length[c];
         a.cdt[c] = a.cm * area * 1e-5 / a.dt;
         af[c] = (T)(area * 1e-2);
-        a.dc[c] = a.cdt[c];
         a.V[c] = a.v_init;
         gm[c] = m0;
         gh[c] = h0;
         gn[c] = n0;
     }
-    a.G[c0] = 0.0;
     a.e[c0] = 0.0;
     for (int32_t i = 1; i < n; ++i) {
         const int64_t c = c0 + i;
@@ -180,11 +197,7 @@ __global__ void k_setup(SetupArgs a) {
         const double rh = 2.0 * a.ra * a.length[c] / (PI * a.diam[c] * a.diam[c]) * 1e-2;
         const double rp = 2.0 * a.ra * a.length[pc] / (PI * a.diam[pc] * a.diam[pc]) * 1e-2;
         const double G = 1.0 / (rh + rp);
-        const double e = -a.theta * G;
-        a.G[c] = G;
-        a.e[c] = e;
-        a.dc[c] -= e;
-        a.dc[pc] -= e;
+        a.e[c] = -a.theta * G;
     }
 }
 
@@ -193,9 +206,9 @@ __global__ void k_setup(SetupArgs a) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct State {
-    double *V, *R, *D, *VO;
+    double *V, *R, *D, *Eo, *VO;
     uint64_t *SM, *SP;
-    T *M, *H, *N, *SG;
+    T *SG;
 };
 
 template <typename T>
@@ -205,15 +218,12 @@ __device__ __forceinline__ State<T> carve(char *base, int n, int s, int k) {
     p.V = dp;
     p.R = dp + n;
     p.D = dp + 2 * n;
-    uint64_t *up = (uint64_t *)(dp + 3 * n);
+    p.Eo = dp + 3 * n;
+    uint64_t *up = (uint64_t *)(dp + 4 * n);
     p.SM = up;
     p.SP = up + s;
     p.VO = (double *)(up + s + k);
-    T *tp = (T *)(p.VO + k);
-    p.M = tp;
-    p.H = tp + n;
-    p.N = tp + 2 * n;
-    p.SG = tp + 3 * n;
+    p.SG = (T *)(p.VO + k);
     return p;
 }
 
@@ -240,45 +250,229 @@ __device__ __forceinline__ uint64_t event_mask(const uint64_t *hist, int32_t N, 
     return m;
 }
 
-template <typename T, bool kGlobal>
-__device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *base,
-                                         int64_t epoch, int pid) {
+// Backward sweep of one branch b0..b1 (Algorithm 1 restricted to the
+// branch): first the contributions of the child branches hanging off b1 in
+// descending base order, then the chain from the tip down to the base. The
+// loads of the next chain element do not depend on the running values and
+// are issued one iteration ahead.
+__device__ __forceinline__ void sweep_back(double *__restrict__ D, double *__restrict__ R,
+                                           const double *__restrict__ Eo, const Branch b,
+                                           const uint16_t *__restrict__ chl) {
+    double dd = D[b.b1], rr = R[b.b1];
+    for (int c = b.nchild - 1; c >= 0; --c) {
+        const int j = chl[b.child0 + c];
+        const double ej = Eo[j];
+        const double f = ej / D[j];
+        dd = dd - f * ej;
+        rr = rr - f * R[j];
+    }
+    int i = b.b1;
+    if (i > b.b0) {
+        double e_c = Eo[i], d_n = D[i - 1], r_n = R[i - 1];
+        for (; i > b.b0; --i) {
+            const int k = i - 2 >= b.b0 ? i - 2 : b.b0;
+            const double e_c2 = Eo[i - 1], d_n2 = D[k], r_n2 = R[k];
+            D[i] = dd;
+            R[i] = rr;
+            const double f = e_c / dd;
+            dd = d_n - f * e_c;
+            rr = r_n - f * rr;
+            e_c = e_c2;
+            d_n = d_n2;
+            r_n = r_n2;
+        }
+    }
+    D[b.b0] = dd;
+    R[b.b0] = rr;
+}
+
+// Correctly rounded t / d given y = RN(1/d): q = RN(t y) is within one ulp of
+// t/d, the residual t - q d is exact in one fused multiply-add, and
+// RN(q + r y) is then the correctly rounded quotient (Markstein's theorem;
+// the operands here are far from the underflow and overflow ranges). This
+// takes the division off the forward chain: y depends only on the finished
+// diagonal and is computed one element ahead.
+__device__ __forceinline__ double div_rn(double t, double d, double y) {
+    const double q = t * y;
+    const double r = __builtin_fma(-q, d, t);
+    return __builtin_fma(r, y, q);
+}
+
+// Forward sweep of one branch: base from its parent's new value, then the
+// chain towards the tip. On entry V[i] holds RN(1/D[i]) for the branch's own
+// compartments (written by the parallel reciprocal phase); each is replaced
+// by the new voltage as the chain passes, so V[par] is already the parent's
+// new voltage.
+__device__ __forceinline__ void sweep_fwd(double *__restrict__ V, const double *__restrict__ D,
+                                          const double *__restrict__ R,
+                                          const double *__restrict__ Eo, const Branch b) {
+    double t = R[b.b0];
+    if (b.par != kRootPar) t = t - Eo[b.b0] * V[b.par];
+    double x = div_rn(t, D[b.b0], V[b.b0]);
+    V[b.b0] = x;
+    if (b.b1 > b.b0) {
+        int i = b.b0 + 1;
+        double r_c = R[i], e_c = Eo[i], d_c = D[i], y_c = V[i];
+        for (; i <= b.b1; ++i) {
+            const int k = i + 1 <= b.b1 ? i + 1 : b.b1;
+            const double r_n = R[k], e_n = Eo[k], d_n = D[k], y_n = V[k];
+            x = div_rn(r_c - e_c * x, d_c, y_c);
+            V[i] = x;
+            r_c = r_n;
+            e_c = e_n;
+            d_c = d_n;
+            y_c = y_n;
+        }
+    }
+}
+
+struct Consts {
+    double omt, vth, ginv;
+};
+
+// Phase B for one compartment: membrane conductance and source from the gates
+// of step n, axial current and diagonal from the couplings to the parent and
+// the children (children in ascending order, as the time-invariant diagonal
+// is defined), then D_i and R_i.
+template <typename T>
+__device__ __forceinline__ void assemble(const int i, const uint32_t tp, const double cdt,
+                                         const T afv, const T m, const T h, const T x,
+                                         double *__restrict__ V, double *__restrict__ R,
+                                         double *__restrict__ D, const double *__restrict__ Eo,
+                                         const Branch *__restrict__ br,
+                                         const uint16_t *__restrict__ chl, const T *niext,
+                                         const int neur0, const T gnabar, const T gkbar,
+                                         const T gl, const T ena, const T ek, const T el,
+                                         const T g_pas, const T e_pas, const T e_syn,
+                                         const Consts c) {
+    const double v = V[i];
+    const T gs = *(const T *)&R[i];
+    T gion, jion;
+    if (topo_hh(tp)) {
+        const T gna = gnabar * (((m * m) * m) * h);
+        const T gk = gkbar * (((x * x) * x) * x);
+        gion = (gna + gk) + gl;
+        jion = (gna * ena + gk * ek) + gl * el;
+    } else {
+        gion = g_pas;
+        jion = g_pas * e_pas;
+    }
+    const bool root = topo_root(tp);
+    const T iext = root ? niext[neur0 + topo_parent(tp)] : T(0);
+    const T gmem = afv * gion + gs;
+    const T J = (afv * jion + gs * e_syn) + iext;
+    double ax, d = cdt;
+    if (root) {
+        ax = 0.0;
+    } else {
+        const double ei = Eo[i];
+        ax = (ei * c.ginv) * (V[topo_parent(tp)] - v);
+        d = d - ei;
+    }
+    const uint32_t bid = topo_branch(tp);
+    if (bid == kNone) {
+        const double e1 = Eo[i + 1];
+        ax = ax - (e1 * c.ginv) * (v - V[i + 1]);
+        d = d - e1;
+    } else {
+        const Branch b = br[bid];
+        for (int q = 0; q < b.nchild; ++q) {
+            const int j = chl[b.child0 + q];
+            const double ej = Eo[j];
+            ax = ax - (ej * c.ginv) * (v - V[j]);
+            d = d - ej;
+        }
+    }
+    D[i] = d + (double)gmem;
+    R[i] = (cdt * v + (double)J) + c.omt * ax;
+}
+
+template <typename T>
+__device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x, const T dt) {
+    const T v = (T)v64;
+    T am, bm, ah, bh, an, bn;
+    hh_rates<T>(v, am, bm, ah, bh, an, bn);
+    m = gate_step<T>(m, am, bm, dt);
+    h = gate_step<T>(h, ah, bh, dt);
+    x = gate_step<T>(x, an, bn, dt);
+}
+
+// The pack's topology tables, staged in LDS for the whole epoch.
+struct Tables {
+    Branch *br;
+    uint16_t *chl, *sched;
+    int32_t *lvl;
+};
+
+__device__ __forceinline__ Tables carve_tables(char *smem, const PackDesc &pk) {
+    Tables t;
+    t.br = (Branch *)smem;
+    t.chl = (uint16_t *)(t.br + pk.nbr);
+    t.sched = t.chl + pk.nch;
+    char *p = (char *)(t.sched + 2 * pk.nbr);
+    t.lvl = (int32_t *)(smem + (((p - smem) + 3) / 4) * 4);
+    return t;
+}
+
+// One pack through steps [t0, t1) of an epoch. V, R, D and the off-diagonal
+// live at `base` (LDS, or a global scratch slice for packs larger than the
+// LDS budget); gates and the per-compartment constants are read from (and
+// the gates written back to) global memory every step, where they stay in
+// the L2/MALL while the pack runs. In the sweeps the branches of a level go
+// to consecutive lanes (sorted by length on the host), so one wave
+// instruction advances as many chains as the level has branches.
+template <typename T>
+__device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
+                                         char *base, int64_t epoch, int pid) {
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
+    const int slot = tid;
     const int n = pk.ncomp, ns = pk.nsyn, nn = pk.nneur;
     const int64_t c0 = pk.comp0, s0 = pk.syn0;
     const State<T> st = carve<T>(base, n, ns, nn);
+    const Tables tb = carve_tables(smem, pk);
+#ifdef MMH_PHASE_PROFILE
+    uint64_t ph_t_ = threadIdx.x == 0 ? wall_clock64() : 0;
+#endif
+    {
+        const Branch *gbr = a.br + pk.br0;
+        for (int k = tid; k < pk.nbr; k += NT) tb.br[k] = gbr[k];
+        const uint16_t *gch = a.chl + pk.ch0;
+        for (int k = tid; k < pk.nch; k += NT) tb.chl[k] = gch[k];
+        const uint16_t *gsc = a.sched + pk.sc0;
+        for (int k = tid; k < 2 * pk.nbr; k += NT) tb.sched[k] = gsc[k];
+        const int32_t *glv = a.lvl + pk.lv0;
+        for (int k = tid; k < pk.nbw + pk.nfw + 2; k += NT) tb.lvl[k] = glv[k];
+    }
     double *__restrict__ V = st.V;
     double *__restrict__ R = st.R;
     double *__restrict__ D = st.D;
-    T *__restrict__ M = st.M;
-    T *__restrict__ H = st.H;
-    T *__restrict__ Ng = st.N;
+    double *__restrict__ Eo = st.Eo;
     T *__restrict__ SG = st.SG;
 
-    const T *gm = (const T *)a.gm, *gh = (const T *)a.gh, *gn = (const T *)a.gn;
-    const T *af = (const T *)a.af;
+    T *gm = (T *)a.gm + c0, *gh = (T *)a.gh + c0, *gn = (T *)a.gn + c0;
+    const T *af = (const T *)a.af + c0;
+    const double *cdtp = a.cdt + c0;
+    const uint32_t *topo = a.topo + c0;
     const T *sw = (const T *)a.sw;
     const T *niext = (const T *)a.niext;
-    const Branch *br = a.br + pk.br0;
-    const uint16_t *chl = a.chl + pk.ch0;
-    const int32_t *lvl = a.lvl + pk.lv0;
-    const uint16_t *sched = a.sched + pk.sc0;
+    const Branch *br = tb.br;
+    const uint16_t *chl = tb.chl;
+    const int32_t *lvl = tb.lvl;
+    const uint16_t *sched = tb.sched;
 
     const T gnabar = (T)a.gnabar, gkbar = (T)a.gkbar, gl = (T)a.gl;
     const T ena = (T)a.ena, ek = (T)a.ek, el = (T)a.el;
     const T g_pas = (T)a.g_pas, e_pas = (T)a.e_pas, e_syn = (T)a.e_syn;
     const T dt = (T)a.dt, q = (T)a.q;
-    const double omt = a.omt, vth = a.v_thresh;
+    const Consts cs{a.omt, a.v_thresh, a.ginv};
     const int t0 = a.t0, t1 = a.t1;
 
     // ---- load state -------------------------------------------------------
     for (int i = tid; i < n; i += NT) {
         V[i] = a.V[c0 + i];
-        M[i] = gm[c0 + i];
-        H[i] = gh[c0 + i];
-        Ng[i] = gn[c0 + i];
-        R[i] = 0.0;  // holds the synaptic conductance of compartment i in phase A/B
+        Eo[i] = a.e[c0 + i];
+        R[i] = 0.0;  // synaptic conductance of compartment i in phases A/B
     }
     for (int k = tid; k < ns; k += NT) {
         SG[k] = ((const T *)a.sg)[s0 + k];
@@ -289,6 +483,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         st.SP[k] = 0ull;
     }
     __syncthreads();
+    MMH_PHASE(0);
 
     for (int t = t0; t < t1; ++t) {
         // ---- A: delivery and per-compartment synaptic conductance ----------
@@ -306,121 +501,59 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             *(T *)&R[a.scomp[s0 + k]] = sum;
         }
         __syncthreads();
+        MMH_PHASE(1);
 
         // ---- B: membrane terms and assembly --------------------------------
-        for (int i = tid; i < n; i += NT) {
-            const int64_t gc = c0 + i;
-            const uint32_t tp = a.topo[gc];
-            const double v = V[i];
-            const T gs = *(const T *)&R[i];
-            T gion, jion;
-            if (topo_hh(tp)) {
-                const T m = M[i], h = H[i], x = Ng[i];
-                const T gna = gnabar * (((m * m) * m) * h);
-                const T gk = gkbar * (((x * x) * x) * x);
-                gion = (gna + gk) + gl;
-                jion = (gna * ena + gk * ek) + gl * el;
-            } else {
-                gion = g_pas;
-                jion = g_pas * e_pas;
-            }
-            const bool root = topo_root(tp);
-            const T iext = root ? niext[pk.neur0 + topo_parent(tp)] : T(0);
-            const T afv = af[gc];
-            const T gmem = afv * gion + gs;
-            const T J = (afv * jion + gs * e_syn) + iext;
-            double ax = root ? 0.0 : a.G[gc] * (V[topo_parent(tp)] - v);
-            const uint32_t bid = topo_branch(tp);
-            if (bid == kNone) {
-                ax = ax - a.G[gc + 1] * (v - V[i + 1]);
-            } else {
-                const Branch b = br[bid];
-                for (int c = 0; c < b.nchild; ++c) {
-                    const int j = chl[b.child0 + c];
-                    ax = ax - a.G[c0 + j] * (v - V[j]);
-                }
-            }
-            D[i] = a.dc[gc] + (double)gmem;
-            R[i] = (a.cdt[gc] * v + (double)J) + omt * ax;
-        }
+        for (int i = tid; i < n; i += NT)
+            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl,
+                        niext, pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
         __syncthreads();
+        MMH_PHASE(2);
 
         // ---- C: backward sweep by height -----------------------------------
         for (int h = 0; h < pk.nbw; ++h) {
-            for (int q2 = lvl[h] + tid; q2 < lvl[h + 1]; q2 += NT) {
-                const Branch b = br[sched[q2]];
-                double dd = D[b.b1], rr = R[b.b1];
-                for (int c = b.nchild - 1; c >= 0; --c) {
-                    const int j = chl[b.child0 + c];
-                    const double ej = a.e[c0 + j];
-                    const double f = ej / D[j];
-                    dd = dd - f * ej;
-                    rr = rr - f * R[j];
-                }
-                for (int i = b.b1; i > b.b0; --i) {
-                    D[i] = dd;
-                    R[i] = rr;
-                    const double ei = a.e[c0 + i];
-                    const double f = ei / dd;
-                    dd = D[i - 1] - f * ei;
-                    rr = R[i - 1] - f * rr;
-                }
-                D[b.b0] = dd;
-                R[b.b0] = rr;
-            }
+            for (int q2 = lvl[h] + slot; q2 < lvl[h + 1]; q2 += NT)
+                sweep_back(D, R, Eo, br[sched[q2]], chl);
             __syncthreads();
         }
+        // reciprocals of the finished diagonal, in parallel (V^n is no longer
+        // needed: detection keeps its own copy)
+        for (int i = tid; i < n; i += NT) V[i] = 1.0 / D[i];
+        __syncthreads();
+        MMH_PHASE(3);
 
         // ---- D: forward sweep by depth -------------------------------------
         const int32_t *flv = lvl + pk.nbw + 1;
         const uint16_t *fsc = sched + pk.nbr;
         for (int h = 0; h < pk.nfw; ++h) {
-            for (int q2 = flv[h] + tid; q2 < flv[h + 1]; q2 += NT) {
-                const Branch b = br[fsc[q2]];
-                const uint32_t tp = a.topo[c0 + b.b0];
-                double x;
-                if (topo_root(tp))
-                    x = R[b.b0] / D[b.b0];
-                else
-                    x = (R[b.b0] - a.e[c0 + b.b0] * V[topo_parent(tp)]) / D[b.b0];
-                V[b.b0] = x;
-                for (int i = b.b0 + 1; i <= b.b1; ++i) {
-                    x = (R[i] - a.e[c0 + i] * x) / D[i];
-                    V[i] = x;
-                }
-            }
+            for (int q2 = flv[h] + slot; q2 < flv[h + 1]; q2 += NT)
+                sweep_fwd(V, D, R, Eo, br[fsc[q2]]);
             __syncthreads();
         }
+        MMH_PHASE(4);
 
         // ---- E: gates at V^{n+1}; detection --------------------------------
         for (int i = tid; i < n; i += NT) {
-            const uint32_t tp = a.topo[c0 + i];
-            if (topo_hh(tp)) {
-                const T v = (T)V[i];
-                T am, bm, ah, bh, an, bn;
-                hh_rates<T>(v, am, bm, ah, bh, an, bn);
-                M[i] = gate_step<T>(M[i], am, bm, dt);
-                H[i] = gate_step<T>(H[i], ah, bh, dt);
-                Ng[i] = gate_step<T>(Ng[i], an, bn, dt);
+            if (topo_hh(topo[i])) {
+                T m = gm[i], h = gh[i], x = gn[i];
+                gates_update<T>(V[i], m, h, x, dt);
+                gm[i] = m;
+                gh[i] = h;
+                gn[i] = x;
             }
             R[i] = 0.0;
         }
         for (int k = tid; k < nn; k += NT) {
             const double vn = V[a.ndet[pk.neur0 + k]];
-            if (st.VO[k] < vth && vn >= vth) st.SP[k] |= 1ull << t;
+            if (st.VO[k] < cs.vth && vn >= cs.vth) st.SP[k] |= 1ull << t;
             st.VO[k] = vn;
         }
         __syncthreads();
+        MMH_PHASE(5);
     }
 
     // ---- write back -----------------------------------------------------------
-    T *ogm = (T *)a.gm, *ogh = (T *)a.gh, *ogn = (T *)a.gn;
-    for (int i = tid; i < n; i += NT) {
-        a.V[c0 + i] = V[i];
-        ogm[c0 + i] = M[i];
-        ogh[c0 + i] = H[i];
-        ogn[c0 + i] = Ng[i];
-    }
+    for (int i = tid; i < n; i += NT) a.V[c0 + i] = V[i];
     if (t1 > t0) {
         T *osg = (T *)a.sg;
         for (int k = tid; k < ns; k += NT) osg[s0 + k] = q * SG[k];
@@ -431,10 +564,12 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             *w = *w | st.SP[k];
         }
     }
+    MMH_PHASE(6);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_epoch(EpochArgs a) {
+__global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
+    k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
     const int64_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
     const int q0 = a.wg_off[blockIdx.x], q1 = a.wg_off[blockIdx.x + 1];
@@ -444,10 +579,10 @@ __global__ void __launch_bounds__(1024) k_epoch(EpochArgs a) {
         uint64_t tstart = 0;
         if (a.pack_time && threadIdx.x == 0) tstart = wall_clock64();
         if (pk.global_mem)
-            run_pack<T, true>(a, pk, a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride,
-                              epoch, pid);
+            run_pack<T>(a, pk, smem, a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride,
+                        epoch, pid);
         else
-            run_pack<T, false>(a, pk, smem, epoch, pid);
+            run_pack<T>(a, pk, smem, smem + pk.tbytes, epoch, pid);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
@@ -500,6 +635,19 @@ hipError_t set_epoch_lds_limit(int bytes) {
                                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     return e1 != hipSuccess ? e1 : e2;
 }
+
+#ifdef MMH_PHASE_PROFILE
+extern "C" int mmh_phase_ticks(unsigned long long *out, int reset) {
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_ticks), sizeof(unsigned long long) * 8) !=
+        hipSuccess)
+        return -1;
+    if (reset) {
+        unsigned long long z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), z, sizeof z) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif
 
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
     if (n <= 0) return hipSuccess;

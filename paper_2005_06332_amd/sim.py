@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmmhines.so")
+LIB_PATH = os.environ.get("MMHINES_LIB") or os.path.join(HERE, "libmmhines.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
 FP64, FP32_GATING = 0, 1
