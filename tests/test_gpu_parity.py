@@ -165,3 +165,23 @@ def test_validation_errors_do_not_touch_the_device(S):
     with pytest.raises(S.SimError) as e:
         S.Simulation(prob, epoch_steps=41)
     assert e.value.code == S.SIM_EINVAL
+
+
+def test_full_size_multimorphology_matches_oracle(S, orc):
+    """The 16384-neuron multi-morphology network (9.29e6 compartments, 1.6e6
+    synapses) in the launch configuration bench.py times (count packing,
+    autotuned layout), 200 steps = 5 epochs, every voltage and every spike
+    against the oracle."""
+    prob = W.make(3)
+    steps = 200
+    say(f"case full cfg3 N={prob['n_comp'].shape[0]} C={int(prob['comp_off'][-1])} steps={steps}")
+    with S.Simulation(prob, packing=S.PACK_COUNT, autotune=True) as g:
+        say("  config:", g.config)
+        g.step(steps)
+        v, s = g.voltages(), g.spikes()
+    ref = orc.Sim(prob, max_steps=steps)
+    ref.step(steps)
+    vr, sr = ref.voltages(), ref.spikes()
+    ref.close()
+    compare("full cfg3", v, vr, s, sr)
+    assert len(sr) > 1000
