@@ -115,6 +115,8 @@ def cpu_baseline(prob: dict, target_s: float = 15.0):
     want = rate * target_s / steps
     mean_n = float(prob["comp_off"][-1]) / n_all
     nn = int(min(n_all, max(256, want / mean_n)))
+    if nn == n_all:  # the whole network fits the budget: run it longer
+        steps = int(min(4000, max(80, rate * target_s / float(prob["comp_off"][-1]))))
     sample = W.subset(prob, np.arange(nn))
     t0 = time.perf_counter()
     s = O.Sim(sample, max_steps=steps)

@@ -115,10 +115,12 @@ typedef struct {
     int32_t autotune;    /* 1: time trial epochs over launch variants at
                             create and keep the fastest */
     int32_t threads;     /* workgroup size 64..1024 (multiple of 64; at most 512
-                            in SIM_FP64), 0 = 512 */
-    int32_t pack_comps;  /* target compartments per pack, 0 = 1400 */
-    int32_t lds_comps;   /* largest pack kept in LDS; larger packs use global
-                            scratch. 0 = derived from the LDS budget */
+                            in SIM_FP64), 0 = 256 */
+    int32_t pack_comps;  /* target compartments per pack, 0 = 800 */
+    int32_t lds_comps;   /* LDS budget of the smallest pack class, in
+                            compartments (the two larger classes get 2x and
+                            4x, capped by the CU's LDS); packs beyond every
+                            budget use global scratch. 0 = 1100 */
     int32_t use_graph;   /* 1: replay whole epochs from a captured hipGraph */
     int32_t record_timings; /* 1: per-pack wall-clock time in the kernel */
     const float *cost_model;   /* MLP parameters (sim_mlp_nparams floats) for

@@ -153,6 +153,17 @@ void features(const NeuronTopo &t, const uint8_t *mech, int32_t nsyn, int32_t ns
 // ---------------------------------------------------------------------------
 // Launch variant and device buffers.
 // ---------------------------------------------------------------------------
+constexpr int kClasses = 3;
+
+// One launch of the epoch kernel over the packs of one size class: its
+// workgroup count, dynamic LDS, and where its lists start in the shared
+// offset / list arrays.
+struct Launch {
+    int n_wg = 0;
+    size_t lds = 256;
+    int32_t off0 = 0, list0 = 0;
+};
+
 struct Variant {
     int threads = 256;
     int pack_comps = 1024;
@@ -216,6 +227,9 @@ struct sim {
     std::vector<int32_t> wg_off, wg_list;
     int n_wg = 0;
     size_t lds_bytes = 0;
+    Launch launch[kClasses];     // one launch per size class
+    hipStream_t side[kClasses] = {};  // streams of classes 1.. (class 0: main stream)
+    hipEvent_t ev_fork = nullptr, ev_join[kClasses] = {};
     int64_t scratch_bytes = 0;
     int max_lds = 64 * 1024;
     int n_cu = 256;
@@ -471,7 +485,15 @@ void build_layout(sim_t *s, Variant v) {
     s->comp_perm.reserve(s->C);
     s->syn_perm.clear();
     s->syn_perm.reserve(s->S);
-    int64_t lds_max = 0, scratch = 0;
+    int64_t scratch = 0;
+    // size classes: LDS budgets lds_limit, 2x, 4x, ... capped at the CU's LDS;
+    // the last class also takes the packs that fit nowhere (global state)
+    int64_t cls_budget[kClasses], lds_cls[kClasses];
+    for (int c = 0; c < kClasses; ++c) {
+        cls_budget[c] = std::min<int64_t>((int64_t)v.lds_limit << c, s->max_lds);
+        lds_cls[c] = 0;
+    }
+    std::vector<int> pclass(npk, 0);
     std::vector<std::pair<int64_t, int64_t>> segs;  // (local comp, synapse id)
 
 
@@ -525,7 +547,7 @@ void build_layout(sim_t *s, Variant v) {
                 r.par = bb == 0 ? kRootPar : (uint16_t)(comp_base + s->parent[b + t.b0[bb]]);
                 r.pad = 0;
                 for (int32_t c = t.child_off[bb]; c < t.child_off[bb + 1]; ++c)
-                    chl.push_back((uint16_t)(comp_base + t.b0[t.child[c]]));
+                    chl.push_back((uint16_t)(br_base + t.child[c]));
                 brs.push_back(r);
                 bh.push_back(t.height[bb]);
                 bd.push_back(t.depth[bb]);
@@ -596,60 +618,86 @@ void build_layout(sim_t *s, Variant v) {
             lvl.push_back((int32_t)(sched.size() - d.sc0 - nbr));
         }
         d.nch = (int32_t)chl.size() - d.ch0;
-        d.tbytes = (int32_t)pack_table_bytes(d.nbr, d.nch, d.nbw + d.nfw + 2);
+        d.tbytes = (int32_t)(s->tsize == 8
+                                 ? pack_table_bytes<double>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn)
+                                 : pack_table_bytes<float>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn));
+        // size class: 0 = fits the small LDS budget (many workgroups per CU),
+        // 1 = needs a larger LDS allocation (its own concurrent launch), or
+        // does not fit LDS at all (state in global scratch, same launch)
         const int64_t bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
-        if (d.tbytes + bytes <= v.lds_limit) {
+        if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
+        int c = 0;
+        while (c + 1 < kClasses && d.tbytes + bytes > cls_budget[c]) ++c;
+        if (d.tbytes + bytes <= cls_budget[c]) {
             d.global_mem = 0;
-            lds_max = std::max(lds_max, d.tbytes + bytes);
+            lds_cls[c] = std::max(lds_cls[c], d.tbytes + bytes);
         } else {
             d.global_mem = 1;
-            lds_max = std::max<int64_t>(lds_max, d.tbytes);
+            lds_cls[c] = std::max<int64_t>(lds_cls[c], d.tbytes);
             scratch = std::max(scratch, bytes);
         }
-        if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
+        pclass[p] = c;
         s->packs[p] = d;
     }
     ncomp0.push_back((int64_t)topo.size());
-    s->lds_bytes = (size_t)std::max<int64_t>(lds_max, 256);
-
     s->scratch_bytes = scratch;
 
-    // workgroup lists
+    // workgroup lists, one per size class
     s->wg_off.clear();
     s->wg_list.clear();
     int sched_mode = v.sched;
     if (s->P.packing == SIM_PACK_PLAIN) sched_mode = SIM_SCHED_DISPATCH;
-    if (sched_mode == SIM_SCHED_DISPATCH) {
-        s->n_wg = npk;
-        for (int p = 0; p <= npk; ++p) s->wg_off.push_back(p);
-        for (int p = 0; p < npk; ++p) s->wg_list.push_back(p);
-    } else {
-        // resident workgroups per CU from the LDS footprint and the thread count
-        const int by_lds = std::max(1, (int)(s->max_lds / std::max<size_t>(s->lds_bytes, 1)));
-        const int by_thr = std::max(1, 2048 / v.threads);
-        const int per_cu = std::max(1, std::min(by_lds, by_thr));
-        s->n_wg = std::max(1, std::min(npk, per_cu * s->n_cu));
-        // LPT: packs by decreasing cost, each to the least loaded workgroup
-        std::vector<int32_t> byc(npk);
-        std::iota(byc.begin(), byc.end(), 0);
-        std::stable_sort(byc.begin(), byc.end(),
-                         [&](int32_t a, int32_t b) { return s->pack_cost[a] > s->pack_cost[b]; });
-        using QE = std::pair<double, int32_t>;
-        std::priority_queue<QE, std::vector<QE>, std::greater<QE>> heap;
-        for (int w = 0; w < s->n_wg; ++w) heap.push({0.0, w});
-        std::vector<std::vector<int32_t>> lists(s->n_wg);
-        for (int32_t p : byc) {
-            QE top = heap.top();
-            heap.pop();
-            lists[top.second].push_back(p);
-            heap.push({top.first + s->pack_cost[p], top.second});
+    for (int c = 0; c < kClasses; ++c) {
+        Launch &L = s->launch[c];
+        L.lds = (size_t)std::max<int64_t>(lds_cls[c], 256);
+        L.off0 = (int32_t)s->wg_off.size();
+        L.list0 = (int32_t)s->wg_list.size();
+        std::vector<int32_t> mine;  // in pack order (cost order for sorted packings)
+        for (int p = 0; p < npk; ++p)
+            if (pclass[p] == c) mine.push_back(p);
+        const int np = (int)mine.size();
+        if (np == 0) {
+            L.n_wg = 0;
+            s->wg_off.push_back(0);
+            continue;
         }
-        s->wg_off.push_back(0);
-        for (int w = 0; w < s->n_wg; ++w) {
-            for (int32_t p : lists[w]) s->wg_list.push_back(p);
-            s->wg_off.push_back((int32_t)s->wg_list.size());
+        if (sched_mode == SIM_SCHED_DISPATCH || c > 0) {
+            L.n_wg = np;
+            for (int q = 0; q <= np; ++q) s->wg_off.push_back(q);
+            for (int p : mine) s->wg_list.push_back(p);
+        } else {
+            // resident workgroups per CU from the LDS footprint and the threads
+            const int by_lds = std::max(1, (int)(s->max_lds / std::max<size_t>(L.lds, 1)));
+            const int by_thr = std::max(1, 2048 / v.threads);
+            const int per_cu = std::max(1, std::min(by_lds, by_thr));
+            L.n_wg = std::max(1, std::min(np, per_cu * s->n_cu));
+            // LPT: packs by decreasing cost, each to the least loaded workgroup
+            std::vector<int32_t> byc = mine;
+            std::stable_sort(byc.begin(), byc.end(), [&](int32_t a, int32_t b) {
+                return s->pack_cost[a] > s->pack_cost[b];
+            });
+            using QE = std::pair<double, int32_t>;
+            std::priority_queue<QE, std::vector<QE>, std::greater<QE>> heap;
+            for (int w = 0; w < L.n_wg; ++w) heap.push({0.0, w});
+            std::vector<std::vector<int32_t>> lists(L.n_wg);
+            for (int32_t p : byc) {
+                QE top = heap.top();
+                heap.pop();
+                lists[top.second].push_back(p);
+                heap.push({top.first + s->pack_cost[p], top.second});
+            }
+            int32_t acc = 0;
+            s->wg_off.push_back(0);
+            for (int w = 0; w < L.n_wg; ++w) {
+                for (int32_t p : lists[w]) s->wg_list.push_back(p);
+                acc += (int32_t)lists[w].size();
+                s->wg_off.push_back(acc);
+            }
         }
     }
+    s->n_wg = 0;
+    for (int c = 0; c < kClasses; ++c) s->n_wg += s->launch[c].n_wg;
+    s->lds_bytes = s->launch[0].lds;
 
     // device upload
     s->d_packs.upload(s->packs);
@@ -820,16 +868,39 @@ void assign_scratch(sim_t *s) {
     }
 }
 
+// One epoch (or part of one): the large-pack class on the second stream and
+// the small-pack class on the main stream run concurrently, forked from and
+// joined back into the main stream (also inside a captured graph).
 void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
-    EpochArgs a = make_args(s);
-    a.epoch = epoch;
-    a.epoch_ptr = use_ptr ? s->d_epoch.p : nullptr;
-    a.t0 = t0;
-    a.t1 = t1;
-    a.scratch_stride = s->scratch_bytes;
-    HIPCHK(launch_epoch(a, s->precision == SIM_FP64 ? 0 : 1, s->n_wg, s->var.threads,
-                        s->lds_bytes,
-                        s->stream));
+    const int pr = s->precision == SIM_FP64 ? 0 : 1;
+    auto args = [&](const Launch &L) {
+        EpochArgs a = make_args(s);
+        a.wg_off = s->d_wg_off.p + L.off0;
+        a.wg_list = s->d_wg_list.p + L.list0;
+        a.epoch = epoch;
+        a.epoch_ptr = use_ptr ? s->d_epoch.p : nullptr;
+        a.t0 = t0;
+        a.t1 = t1;
+        a.scratch_stride = s->scratch_bytes;
+        return a;
+    };
+    bool forked = false;
+    for (int c = kClasses - 1; c >= 1; --c) {  // largest packs first
+        const Launch &L = s->launch[c];
+        if (L.n_wg == 0) continue;
+        if (!forked) {
+            HIPCHK(hipEventRecord(s->ev_fork, s->stream));
+            forked = true;
+        }
+        HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
+        HIPCHK(launch_epoch(args(L), pr, L.n_wg, s->var.threads, L.lds, s->side[c]));
+        HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
+    }
+    const Launch &S0 = s->launch[0];
+    if (S0.n_wg > 0)
+        HIPCHK(launch_epoch(args(S0), pr, S0.n_wg, s->var.threads, S0.lds, s->stream));
+    for (int c = 1; c < kClasses; ++c)
+        if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
 }
 
 void capture(sim_t *s, int epochs, hipGraph_t &g, hipGraphExec_t &ex) {
@@ -895,11 +966,12 @@ std::string describe(const sim_t *s) {
     for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
     snprintf(buf, sizeof buf,
              "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d "
-             "wg=%d lds_bytes=%zu E=%d precision=%s packing=%s",
+             "wg=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s packing=%s",
              s->var.threads, s->var.pack_comps, s->var.lds_limit,
              (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
                                                                                     : "persistent",
-             s->packs.size(), nglob, s->n_wg, s->lds_bytes, s->E,
+             s->packs.size(), nglob, s->launch[0].n_wg, s->launch[1].n_wg, s->launch[2].n_wg,
+             s->launch[0].lds, s->launch[1].lds, s->launch[2].lds, s->E,
              s->precision == SIM_FP64 ? "fp64" : "fp32-gating",
              s->P.packing == SIM_PACK_PLAIN ? "plain"
              : s->P.packing == SIM_PACK_COUNT ? "count"
@@ -918,18 +990,26 @@ void apply_variant(sim_t *s, const Variant &v) {
 // Autotuning: time one epoch of each candidate from the initial state, keep
 // the fastest, then re-initialise. Candidates never change results: they only
 // move neurons between workgroups or memory spaces.
+// LDS budget of a pack class: the bytes of a pack of `comps` compartments
+// with a typical synapse count.
+int lds_for(const sim_t *s, int comps) {
+    return (int)std::min<int64_t>(s->max_lds, state_bytes(s, comps, comps / 4 + 16, 64));
+}
+
 void autotune(sim_t *s, Variant base) {
+    // (pack_comps, LDS budget in compartments): small packs keep more
+    // workgroups resident per CU, which hides the latency of the sweeps
+    static const int kShapes[][2] = {{600, 800}, {800, 1100}, {1000, 1300}, {1400, 1800}};
     std::vector<Variant> cand;
-    for (int thr : {256, 512})
-        for (int pc : {1024, 1400, 2048})
-            for (int lds : {64 * 1024, 80 * 1024}) {
-                Variant v = base;
-                v.threads = thr;
-                v.pack_comps = pc;
-                v.lds_limit = std::min(lds, s->max_lds);
-                v.sched = SIM_SCHED_DISPATCH;
-                cand.push_back(v);
-            }
+    for (int thr : {128, 256})
+        for (const auto &sh : kShapes) {
+            Variant v = base;
+            v.threads = thr;
+            v.pack_comps = sh[0];
+            v.lds_limit = lds_for(s, sh[1]);
+            v.sched = SIM_SCHED_DISPATCH;
+            cand.push_back(v);
+        }
     {
         Variant v = base;
         v.sched = SIM_SCHED_PERSISTENT;
@@ -1018,17 +1098,19 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
             HIPCHK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
             s->own_stream = true;
         }
+        HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+        for (int c = 1; c < kClasses; ++c) {
+            HIPCHK(hipStreamCreateWithFlags(&s->side[c], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_join[c], hipEventDisableTiming));
+        }
         HIPCHK(hipEventCreate(&s->ev0));
         HIPCHK(hipEventCreate(&s->ev1));
         s->d_epoch.alloc(1);
         compute_cost(s);
         Variant v;
-        v.threads = params->threads ? params->threads : 512;
-        v.pack_comps = params->pack_comps ? params->pack_comps : 1400;
-        v.lds_limit = params->lds_comps
-                          ? (int)std::min<int64_t>(s->max_lds,
-                                                   state_bytes(s, params->lds_comps, params->lds_comps / 4 + 16, 64))
-                          : std::min(72 * 1024, s->max_lds);
+        v.threads = params->threads ? params->threads : 256;
+        v.pack_comps = params->pack_comps ? params->pack_comps : 800;
+        v.lds_limit = lds_for(s, params->lds_comps ? params->lds_comps : 1100);
         v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
         if (params->autotune)
             autotune(s, v);
@@ -1212,6 +1294,11 @@ void sim_destroy(sim_t *s) {
     fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
     fr(s->d_sseg); fr(s->d_chl); fr(s->d_sched); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
     fr(s->d_hist); fr(s->d_ptime);
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    for (int c = 1; c < kClasses; ++c) {
+        if (s->ev_join[c]) (void)hipEventDestroy(s->ev_join[c]);
+        if (s->side[c]) (void)hipStreamDestroy(s->side[c]);
+    }
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);

@@ -31,9 +31,9 @@ __host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh
 
 // A branch: a maximal run b0..b1 of consecutive compartments where each one
 // is the only child of the previous. Its children (branches whose base hangs
-// off b1) are listed by base compartment, ascending, at child list entries
-// child0 .. child0+nchild-1. par is the parent compartment of b0, or kRootPar
-// when b0 is the root of its neuron.
+// off b1) are listed by branch id, in ascending order of their bases, at
+// child list entries child0 .. child0+nchild-1. par is the parent
+// compartment of b0, or kRootPar when b0 is the root of its neuron.
 constexpr uint16_t kRootPar = 0xFFFF;
 struct Branch {
     uint16_t b0, b1, child0, nchild, par, pad;
@@ -111,12 +111,16 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
     b += ((int64_t)sizeof(T) * s + 15) / 16 * 16;  // synaptic conductances
     return b;
 }
-// Bytes of the pack's topology tables staged next to the state: branch
-// records, child list, schedule (two orders) and level offsets.
-__host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev) {
-    int64_t b = (int64_t)sizeof(Branch) * nbr;
-    b += 2 * nch + 2 * 2 * nbr;
+// Bytes of the pack's tables staged in LDS next to the state: per-branch
+// child contributions (2 doubles), synapse weights (T), level offsets, branch
+// records, child lists, schedule (two orders), synapse targets and run
+// lengths. Must match the carve-up in the kernel.
+template <typename T>
+__host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
+                                                    int64_t nsyn) {
+    int64_t b = 16 * nbr + (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
+    b += (int64_t)sizeof(Branch) * nbr + 2 * nch + 2 * 2 * nbr + 2 * 2 * nsyn;
     return (b + 15) / 16 * 16;
 }
 

@@ -250,21 +250,39 @@ __device__ __forceinline__ uint64_t event_mask(const uint64_t *hist, int32_t N, 
     return m;
 }
 
+// Correctly rounded a / b without range scaling: hardware reciprocal, two
+// Newton steps and one exact-residual correction. This is the sequence the
+// compiler emits for IEEE division with its range-scaling and special-case
+// steps removed; those are identities unless |a|, |b| or the quotient come
+// near the overflow or underflow limits, which the coefficients of a
+// compartmental model (conductances in uS, voltages in mV) never do.
+__device__ __forceinline__ double div_nr(double a, double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = a * y;
+    const double r = __builtin_fma(-b, q, a);
+    return __builtin_fma(r, y, q);
+}
+
 // Backward sweep of one branch b0..b1 (Algorithm 1 restricted to the
-// branch): first the contributions of the child branches hanging off b1 in
-// descending base order, then the chain from the tip down to the base. The
-// loads of the next chain element do not depend on the running values and
-// are issued one iteration ahead.
+// branch): the tip first takes the contributions f*e and f*r of its child
+// branches in descending base order (each child branch left them in CD/CR
+// when it finished), then the chain runs from the tip down to the base, and
+// the base leaves its own contribution to its parent. The loads of the next
+// chain element do not depend on the running values and are issued one
+// iteration ahead.
 __device__ __forceinline__ void sweep_back(double *__restrict__ D, double *__restrict__ R,
                                            const double *__restrict__ Eo, const Branch b,
-                                           const uint16_t *__restrict__ chl) {
+                                           const int bid, const uint16_t *__restrict__ chl,
+                                           double *__restrict__ CD, double *__restrict__ CR) {
     double dd = D[b.b1], rr = R[b.b1];
     for (int c = b.nchild - 1; c >= 0; --c) {
-        const int j = chl[b.child0 + c];
-        const double ej = Eo[j];
-        const double f = ej / D[j];
-        dd = dd - f * ej;
-        rr = rr - f * R[j];
+        const int cid = chl[b.child0 + c];
+        dd = dd - CD[cid];
+        rr = rr - CR[cid];
     }
     int i = b.b1;
     if (i > b.b0) {
@@ -274,7 +292,7 @@ __device__ __forceinline__ void sweep_back(double *__restrict__ D, double *__res
             const double e_c2 = Eo[i - 1], d_n2 = D[k], r_n2 = R[k];
             D[i] = dd;
             R[i] = rr;
-            const double f = e_c / dd;
+            const double f = div_nr(e_c, dd);
             dd = d_n - f * e_c;
             rr = r_n - f * rr;
             e_c = e_c2;
@@ -284,6 +302,12 @@ __device__ __forceinline__ void sweep_back(double *__restrict__ D, double *__res
     }
     D[b.b0] = dd;
     R[b.b0] = rr;
+    if (b.par != kRootPar) {
+        const double e0 = Eo[b.b0];
+        const double f = div_nr(e0, dd);
+        CD[bid] = f * e0;
+        CR[bid] = f * rr;
+    }
 }
 
 // Correctly rounded t / d given y = RN(1/d): q = RN(t y) is within one ulp of
@@ -377,7 +401,7 @@ __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const d
     } else {
         const Branch b = br[bid];
         for (int q = 0; q < b.nchild; ++q) {
-            const int j = chl[b.child0 + q];
+            const int j = br[chl[b.child0 + q]].b0;
             const double ej = Eo[j];
             ax = ax - (ej * c.ginv) * (v - V[j]);
             d = d - ej;
@@ -397,30 +421,43 @@ __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x,
     x = gate_step<T>(x, an, bn, dt);
 }
 
-// The pack's topology tables, staged in LDS for the whole epoch.
+// The pack's tables, staged in LDS for the whole epoch: per-branch child
+// contributions (CD, CR), synapse weights, branch records, child lists,
+// schedule, level offsets, synapse targets and run lengths. The layout must
+// match pack_table_bytes().
+template <typename T>
 struct Tables {
+    double *CD, *CR;
+    T *sw;
     Branch *br;
-    uint16_t *chl, *sched;
+    uint16_t *chl, *sched, *scomp, *sseg;
     int32_t *lvl;
 };
 
-__device__ __forceinline__ Tables carve_tables(char *smem, const PackDesc &pk) {
-    Tables t;
-    t.br = (Branch *)smem;
+template <typename T>
+__device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk) {
+    Tables<T> t;
+    t.CD = (double *)smem;
+    t.CR = t.CD + pk.nbr;
+    t.sw = (T *)(t.CR + pk.nbr);
+    char *p = (char *)(t.sw + pk.nsyn);
+    p = smem + (((p - smem) + 3) / 4) * 4;
+    t.lvl = (int32_t *)p;
+    t.br = (Branch *)(t.lvl + pk.nbw + pk.nfw + 2);
     t.chl = (uint16_t *)(t.br + pk.nbr);
     t.sched = t.chl + pk.nch;
-    char *p = (char *)(t.sched + 2 * pk.nbr);
-    t.lvl = (int32_t *)(smem + (((p - smem) + 3) / 4) * 4);
+    t.scomp = t.sched + 2 * pk.nbr;
+    t.sseg = t.scomp + pk.nsyn;
     return t;
 }
 
 // One pack through steps [t0, t1) of an epoch. V, R, D and the off-diagonal
-// live at `base` (LDS, or a global scratch slice for packs larger than the
-// LDS budget); gates and the per-compartment constants are read from (and
-// the gates written back to) global memory every step, where they stay in
-// the L2/MALL while the pack runs. In the sweeps the branches of a level go
-// to consecutive lanes (sorted by length on the host), so one wave
-// instruction advances as many chains as the level has branches.
+// live at `base` (LDS, or a global scratch slice for packs larger than any
+// LDS budget); gates and per-compartment constants stay in global memory
+// (keeping them in registers costs more occupancy than it saves latency).
+// In the sweeps the branches of a level go to consecutive lanes (sorted by
+// length on the host), so one wave instruction advances as many chains as
+// the level has branches.
 template <typename T>
 __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
                                          char *base, int64_t epoch, int pid) {
@@ -430,7 +467,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const int n = pk.ncomp, ns = pk.nsyn, nn = pk.nneur;
     const int64_t c0 = pk.comp0, s0 = pk.syn0;
     const State<T> st = carve<T>(base, n, ns, nn);
-    const Tables tb = carve_tables(smem, pk);
+    const Tables<T> tb = carve_tables<T>(smem, pk);
 #ifdef MMH_PHASE_PROFILE
     uint64_t ph_t_ = threadIdx.x == 0 ? wall_clock64() : 0;
 #endif
@@ -443,6 +480,12 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         for (int k = tid; k < 2 * pk.nbr; k += NT) tb.sched[k] = gsc[k];
         const int32_t *glv = a.lvl + pk.lv0;
         for (int k = tid; k < pk.nbw + pk.nfw + 2; k += NT) tb.lvl[k] = glv[k];
+        const T *gsw = (const T *)a.sw + s0;
+        for (int k = tid; k < ns; k += NT) {
+            tb.sw[k] = gsw[k];
+            tb.scomp[k] = a.scomp[s0 + k];
+            tb.sseg[k] = a.sseg[s0 + k];
+        }
     }
     double *__restrict__ V = st.V;
     double *__restrict__ R = st.R;
@@ -454,7 +497,6 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const T *af = (const T *)a.af + c0;
     const double *cdtp = a.cdt + c0;
     const uint32_t *topo = a.topo + c0;
-    const T *sw = (const T *)a.sw;
     const T *niext = (const T *)a.niext;
     const Branch *br = tb.br;
     const uint16_t *chl = tb.chl;
@@ -488,37 +530,40 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     for (int t = t0; t < t1; ++t) {
         // ---- A: delivery and per-compartment synaptic conductance ----------
         for (int k = tid; k < ns; k += NT) {
-            const int L = a.sseg[s0 + k];
+            const int L = tb.sseg[k];
             if (L == 0) continue;
             T sum = T(0);
             for (int j = k; j < k + L; ++j) {
                 T g = SG[j];
                 if (t > t0) g = q * g;
-                if ((st.SM[j] >> t) & 1ull) g = g + sw[s0 + j];
+                if ((st.SM[j] >> t) & 1ull) g = g + tb.sw[j];
                 SG[j] = g;
                 sum = sum + g;
             }
-            *(T *)&R[a.scomp[s0 + k]] = sum;
+            *(T *)&R[tb.scomp[k]] = sum;
         }
         __syncthreads();
         MMH_PHASE(1);
 
         // ---- B: membrane terms and assembly --------------------------------
+#pragma unroll 2
         for (int i = tid; i < n; i += NT)
-            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl,
-                        niext, pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
+            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl, niext,
+                        pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
         __syncthreads();
         MMH_PHASE(2);
 
         // ---- C: backward sweep by height -----------------------------------
         for (int h = 0; h < pk.nbw; ++h) {
-            for (int q2 = lvl[h] + slot; q2 < lvl[h + 1]; q2 += NT)
-                sweep_back(D, R, Eo, br[sched[q2]], chl);
+            for (int q2 = lvl[h] + slot; q2 < lvl[h + 1]; q2 += NT) {
+                const int bid = sched[q2];
+                sweep_back(D, R, Eo, br[bid], bid, chl, tb.CD, tb.CR);
+            }
             __syncthreads();
         }
         // reciprocals of the finished diagonal, in parallel (V^n is no longer
         // needed: detection keeps its own copy)
-        for (int i = tid; i < n; i += NT) V[i] = 1.0 / D[i];
+        for (int i = tid; i < n; i += NT) V[i] = div_nr(1.0, D[i]);
         __syncthreads();
         MMH_PHASE(3);
 
@@ -533,6 +578,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         MMH_PHASE(4);
 
         // ---- E: gates at V^{n+1}; detection --------------------------------
+#pragma unroll 2
         for (int i = tid; i < n; i += NT) {
             if (topo_hh(topo[i])) {
                 T m = gm[i], h = gh[i], x = gn[i];
@@ -578,11 +624,9 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         const PackDesc pk = a.packs[pid];
         uint64_t tstart = 0;
         if (a.pack_time && threadIdx.x == 0) tstart = wall_clock64();
-        if (pk.global_mem)
-            run_pack<T>(a, pk, smem, a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride,
-                        epoch, pid);
-        else
-            run_pack<T>(a, pk, smem, smem + pk.tbytes, epoch, pid);
+        char *base = pk.global_mem ? a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride
+                                   : smem + pk.tbytes;
+        run_pack<T>(a, pk, smem, base, epoch, pid);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
@@ -629,11 +673,11 @@ hipError_t launch_epoch(const EpochArgs &a, int precision, int n_wg, int threads
 }
 
 hipError_t set_epoch_lds_limit(int bytes) {
-    hipError_t e1 = hipFuncSetAttribute((const void *)k_epoch<double>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    hipError_t e2 = hipFuncSetAttribute((const void *)k_epoch<float>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    return e1 != hipSuccess ? e1 : e2;
+    hipError_t e = hipFuncSetAttribute((const void *)k_epoch<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_epoch<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 #ifdef MMH_PHASE_PROFILE
