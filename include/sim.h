@@ -48,6 +48,14 @@ extern "C" {
 #define SIM_FP32_GATING 1   /* gates, rates, currents, synaptic g in float;
                                voltage, assembly and Hines solve in double */
 
+#define SIM_SOLVE_EXACT 0   /* elimination in the operation order of the
+                               paper's Algorithm 1 (a division per
+                               compartment on the dependent chain) */
+#define SIM_SOLVE_FAST 1    /* the same elimination in division-free
+                               homogeneous form: one fused multiply-add per
+                               compartment on each dependent chain; agrees
+                               with the exact order to rounding */
+
 #define SIM_PACK_PLAIN 0    /* neurons in input order, one workgroup per pack,
                                hardware dispatch order */
 #define SIM_PACK_COUNT 1    /* cost = compartment count; sort + LPT */
@@ -108,6 +116,7 @@ typedef struct {
     double v_thresh_mV;  /* spike when V crosses it upward at the detector */
     double v_init_mV;    /* initial voltage; gates start at steady state */
     int32_t precision;   /* SIM_FP64 | SIM_FP32_GATING */
+    int32_t solver;      /* SIM_SOLVE_EXACT | SIM_SOLVE_FAST */
     int32_t packing;     /* SIM_PACK_* */
     int32_t sched;       /* SIM_SCHED_* */
     int32_t epoch_steps; /* 0: min(delay) capped at 64; else 1..min(delay),

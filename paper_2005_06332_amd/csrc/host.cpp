@@ -205,6 +205,7 @@ struct sim {
     std::vector<uint8_t> mech;
     std::vector<float> cost_model;
     int precision = 1;
+    int solver = 0;
     int E = 40;
     int tsize = 4;  // sizeof gating type
 
@@ -290,6 +291,8 @@ void validate(const sim_params_t *P, const sim_morphology_t *M, const sim_channe
         throw fail(SIM_EINVAL, "cm and ra must be > 0");
     if (P->precision != SIM_FP64 && P->precision != SIM_FP32_GATING)
         throw fail(SIM_EINVAL, "unknown precision %d", P->precision);
+    if (P->solver != SIM_SOLVE_EXACT && P->solver != SIM_SOLVE_FAST)
+        throw fail(SIM_EINVAL, "unknown solver %d", P->solver);
     if (P->packing < SIM_PACK_PLAIN || P->packing > SIM_PACK_LEARNED)
         throw fail(SIM_EINVAL, "unknown packing %d", P->packing);
     if (P->sched < SIM_SCHED_AUTO || P->sched > SIM_SCHED_DISPATCH)
@@ -374,6 +377,7 @@ void copy_inputs(sim_t *s, const sim_params_t *P, const sim_morphology_t *M,
     }
     if (P->cost_model) s->cost_model.assign(P->cost_model, P->cost_model + kMlpParams);
     s->precision = P->precision;
+    s->solver = P->solver;
     s->tsize = P->precision == SIM_FP64 ? 8 : 4;
     int64_t mind = 64;
     for (int64_t k = 0; k < s->S; ++k) mind = std::min<int64_t>(mind, s->delay[k]);
@@ -893,12 +897,12 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
             forked = true;
         }
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
-        HIPCHK(launch_epoch(args(L), pr, L.n_wg, s->var.threads, L.lds, s->side[c]));
+        HIPCHK(launch_epoch(args(L), pr, s->solver, L.n_wg, s->var.threads, L.lds, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
     const Launch &S0 = s->launch[0];
     if (S0.n_wg > 0)
-        HIPCHK(launch_epoch(args(S0), pr, S0.n_wg, s->var.threads, S0.lds, s->stream));
+        HIPCHK(launch_epoch(args(S0), pr, s->solver, S0.n_wg, s->var.threads, S0.lds, s->stream));
     for (int c = 1; c < kClasses; ++c)
         if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
 }
@@ -966,13 +970,14 @@ std::string describe(const sim_t *s) {
     for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
     snprintf(buf, sizeof buf,
              "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d "
-             "wg=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s packing=%s",
+             "wg=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s solver=%s packing=%s",
              s->var.threads, s->var.pack_comps, s->var.lds_limit,
              (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
                                                                                     : "persistent",
              s->packs.size(), nglob, s->launch[0].n_wg, s->launch[1].n_wg, s->launch[2].n_wg,
              s->launch[0].lds, s->launch[1].lds, s->launch[2].lds, s->E,
              s->precision == SIM_FP64 ? "fp64" : "fp32-gating",
+             s->solver == SIM_SOLVE_FAST ? "fast" : "exact",
              s->P.packing == SIM_PACK_PLAIN ? "plain"
              : s->P.packing == SIM_PACK_COUNT ? "count"
              : s->cost_model.empty() ? "learned(fallback count)" : "learned");
@@ -987,14 +992,15 @@ void apply_variant(sim_t *s, const Variant &v) {
     s->config = describe(s);
 }
 
-// Autotuning: time one epoch of each candidate from the initial state, keep
-// the fastest, then re-initialise. Candidates never change results: they only
-// move neurons between workgroups or memory spaces.
 // LDS budget of a pack class: the bytes of a pack of `comps` compartments
 // with a typical synapse count.
 int lds_for(const sim_t *s, int comps) {
     return (int)std::min<int64_t>(s->max_lds, state_bytes(s, comps, comps / 4 + 16, 64));
 }
+
+// Autotuning: time one epoch of each candidate from the initial state, keep
+// the fastest, then re-initialise. Candidates never change results: they only
+// move neurons between workgroups or memory spaces.
 
 void autotune(sim_t *s, Variant base) {
     // (pack_comps, LDS budget in compartments): small packs keep more
@@ -1053,6 +1059,7 @@ void sim_default_params(sim_params_t *p) {
     p->v_thresh_mV = 0.0;
     p->v_init_mV = -65.0;
     p->precision = SIM_FP32_GATING;
+    p->solver = SIM_SOLVE_EXACT;
     p->packing = SIM_PACK_COUNT;
     p->sched = SIM_SCHED_AUTO;
     p->use_graph = 1;

@@ -109,6 +109,7 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
     int64_t b = 4 * 8 * n;                 // V, R, D, off-diagonal
     b += 8 * s + 8 * k + 8 * k;            // synapse masks, spike masks, V_det
     b += ((int64_t)sizeof(T) * s + 15) / 16 * 16;  // synaptic conductances
+    b += 64;  // slack: the blocked sweeps read up to 3 doubles past a branch
     return b;
 }
 // Bytes of the pack's tables staged in LDS next to the state: per-branch
@@ -138,7 +139,8 @@ struct SetupArgs {
 
 // Launchers (kernels.hip).
 hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s);
-hipError_t launch_epoch(const EpochArgs &a, int precision, int n_wg, int threads,
+// solver: 0 = exact operation order of the elimination, 1 = division-free
+hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg, int threads,
                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_advance(int64_t *epoch, hipStream_t s);

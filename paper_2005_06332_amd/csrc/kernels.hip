@@ -267,49 +267,6 @@ __device__ __forceinline__ double div_nr(double a, double b) {
     return __builtin_fma(r, y, q);
 }
 
-// Backward sweep of one branch b0..b1 (Algorithm 1 restricted to the
-// branch): the tip first takes the contributions f*e and f*r of its child
-// branches in descending base order (each child branch left them in CD/CR
-// when it finished), then the chain runs from the tip down to the base, and
-// the base leaves its own contribution to its parent. The loads of the next
-// chain element do not depend on the running values and are issued one
-// iteration ahead.
-__device__ __forceinline__ void sweep_back(double *__restrict__ D, double *__restrict__ R,
-                                           const double *__restrict__ Eo, const Branch b,
-                                           const int bid, const uint16_t *__restrict__ chl,
-                                           double *__restrict__ CD, double *__restrict__ CR) {
-    double dd = D[b.b1], rr = R[b.b1];
-    for (int c = b.nchild - 1; c >= 0; --c) {
-        const int cid = chl[b.child0 + c];
-        dd = dd - CD[cid];
-        rr = rr - CR[cid];
-    }
-    int i = b.b1;
-    if (i > b.b0) {
-        double e_c = Eo[i], d_n = D[i - 1], r_n = R[i - 1];
-        for (; i > b.b0; --i) {
-            const int k = i - 2 >= b.b0 ? i - 2 : b.b0;
-            const double e_c2 = Eo[i - 1], d_n2 = D[k], r_n2 = R[k];
-            D[i] = dd;
-            R[i] = rr;
-            const double f = div_nr(e_c, dd);
-            dd = d_n - f * e_c;
-            rr = r_n - f * rr;
-            e_c = e_c2;
-            d_n = d_n2;
-            r_n = r_n2;
-        }
-    }
-    D[b.b0] = dd;
-    R[b.b0] = rr;
-    if (b.par != kRootPar) {
-        const double e0 = Eo[b.b0];
-        const double f = div_nr(e0, dd);
-        CD[bid] = f * e0;
-        CR[bid] = f * rr;
-    }
-}
-
 // Correctly rounded t / d given y = RN(1/d): q = RN(t y) is within one ulp of
 // t/d, the residual t - q d is exact in one fused multiply-add, and
 // RN(q + r y) is then the correctly rounded quotient (Markstein's theorem;
@@ -322,30 +279,160 @@ __device__ __forceinline__ double div_rn(double t, double d, double y) {
     return __builtin_fma(r, y, q);
 }
 
-// Forward sweep of one branch: base from its parent's new value, then the
-// chain towards the tip. On entry V[i] holds RN(1/D[i]) for the branch's own
-// compartments (written by the parallel reciprocal phase); each is replaced
-// by the new voltage as the chain passes, so V[par] is already the parent's
-// new voltage.
-__device__ __forceinline__ void sweep_fwd(double *__restrict__ V, const double *__restrict__ D,
-                                          const double *__restrict__ R,
-                                          const double *__restrict__ Eo, const Branch b) {
-    double t = R[b.b0];
-    if (b.par != kRootPar) t = t - Eo[b.b0] * V[b.par];
-    double x = div_rn(t, D[b.b0], V[b.b0]);
+// Reciprocal to about one ulp: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+
+// Fast solver, between the sweeps: from (P, Q, S) of compartment i form
+// g_i = e_i / d'_i (into D) and h_i = r'_i / d'_i (into R), independently
+// for every compartment.
+__device__ __forceinline__ void pivots_h(double *__restrict__ D, double *__restrict__ R,
+                                         const double *__restrict__ Q,
+                                         const double *__restrict__ Eo, int i) {
+    const double y = rcp_nr(D[i]);
+    D[i] = (Eo[i] * Q[i]) * y;
+    R[i] = R[i] * y;
+}
+
+// Both sweeps walk a branch in blocks of kBlk compartments. The block's
+// coefficients are read from LDS together (constant offsets from one
+// address, one round trip per block), then the dependent chain runs in
+// registers and each compartment's result is stored under a per-lane mask.
+// A lane whose branch ends inside a block reads up to kBlk-1 doubles beyond
+// the branch (inside the pack's arrays, or the slack after them) and runs
+// its chain on those values without storing anything; the values it needs
+// afterwards are read back from LDS.
+#ifndef MMH_SWEEP_BLOCK
+#define MMH_SWEEP_BLOCK 4
+#endif
+constexpr int kBlk = MMH_SWEEP_BLOCK;
+
+// The elimination along one branch, tip b1 down to base b0. kFast = false:
+// the operation order of the elimination, a correctly rounded division per
+// compartment (pivot d'_i, reduced right-hand side r'_i left in D and R).
+// kFast = true: the division-free homogeneous form. Along a branch the
+// pivots obey d'_{i-1} = D_{i-1} - e_i^2 / d'_i and the reduced right-hand
+// sides r'_{i-1} = R_{i-1} - e_i r'_i / d'_i; with d'_i = P_i / Q_i and
+// r'_i = S_i / Q_i (one common denominator) both become linear recurrences,
+//   P_{i-1} = D_{i-1} P_i - e_i^2 Q_i,  S_{i-1} = R_{i-1} P_i - e_i S_i,
+//   Q_{i-1} = P_i,
+// one fused multiply-add per compartment on each dependent chain. (P, Q, S)
+// is rescaled by a power of two (exact) after every block, and left in D, R
+// and Q (the V slot). The tip first subtracts the contributions of its child
+// branches (in descending base order); the base leaves e^2/d' and e r'/d'
+// for its parent.
+template <bool kFast>
+__device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *__restrict__ R,
+                                               double *__restrict__ Q,
+                                               const double *__restrict__ Eo, const Branch b,
+                                               const int bid, const uint16_t *__restrict__ chl,
+                                               double *__restrict__ CD, double *__restrict__ CR) {
+    double P = D[b.b1], S = R[b.b1];
+    for (int c = b.nchild - 1; c >= 0; --c) {
+        const int cid = chl[b.child0 + c];
+        P = P - CD[cid];
+        S = S - CR[cid];
+    }
+    double q = 1.0;
+    D[b.b1] = P;
+    R[b.b1] = S;
+    if constexpr (kFast) Q[b.b1] = q;
+    for (int i = b.b1; i > b.b0; i -= kBlk) {
+        const double *pe = Eo + i - (kBlk - 1);
+        double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
+        double e[kBlk], dn[kBlk], rn[kBlk];
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {  // compartment i-1-j
+            e[j] = pe[kBlk - 1 - j];
+            dn[j] = pd[kBlk - 1 - j];
+            rn[j] = pr[kBlk - 1 - j];
+        }
+        const int nv = i - b.b0;
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            if constexpr (kFast) {
+                const double Pn = __builtin_fma(dn[j], P, -(e[j] * e[j]) * q);
+                const double Sn = __builtin_fma(-e[j], S, rn[j] * P);
+                q = P;
+                P = Pn;
+                S = Sn;
+            } else {
+                const double f = div_nr(e[j], P);
+                P = dn[j] - f * e[j];
+                S = rn[j] - f * S;
+            }
+            if (j < nv) {
+                pd[kBlk - 1 - j] = P;
+                pr[kBlk - 1 - j] = S;
+                if constexpr (kFast) pq[kBlk - 1 - j] = q;
+            }
+        }
+        if constexpr (kFast) {
+            const int x = -__builtin_amdgcn_frexp_exp(P);
+            P = __builtin_amdgcn_ldexp(P, x);
+            q = __builtin_amdgcn_ldexp(q, x);
+            S = __builtin_amdgcn_ldexp(S, x);
+        }
+    }
+    if (b.par != kRootPar) {
+        const double e0 = Eo[b.b0];
+        const double P0 = D[b.b0], S0 = R[b.b0];
+        if constexpr (kFast) {
+            const double y = rcp_nr(P0);
+            CD[bid] = ((e0 * e0) * Q[b.b0]) * y;
+            CR[bid] = (e0 * S0) * y;
+        } else {
+            const double f = div_nr(e0, P0);
+            CD[bid] = f * e0;
+            CR[bid] = f * S0;
+        }
+    }
+}
+
+// Back-substitution along one branch, base to tip. Exact: V holds RN(1/d')
+// of the branch's own compartments on entry, x_i = (r'_i - e_i x_parent) /
+// d'_i correctly rounded. Fast: D and R hold g = e/d' and h = r'/d', x_i =
+// h_i - g_i x_parent. V[par] is already the parent's new voltage.
+template <bool kFast>
+__device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const double *__restrict__ D,
+                                              const double *__restrict__ R,
+                                              const double *__restrict__ Eo, const Branch b) {
+    double x;
+    if constexpr (kFast) {
+        x = R[b.b0];
+        if (b.par != kRootPar) x = __builtin_fma(-D[b.b0], V[b.par], x);
+    } else {
+        double t = R[b.b0];
+        if (b.par != kRootPar) t = t - Eo[b.b0] * V[b.par];
+        x = div_rn(t, D[b.b0], V[b.b0]);
+    }
     V[b.b0] = x;
-    if (b.b1 > b.b0) {
-        int i = b.b0 + 1;
-        double r_c = R[i], e_c = Eo[i], d_c = D[i], y_c = V[i];
-        for (; i <= b.b1; ++i) {
-            const int k = i + 1 <= b.b1 ? i + 1 : b.b1;
-            const double r_n = R[k], e_n = Eo[k], d_n = D[k], y_n = V[k];
-            x = div_rn(r_c - e_c * x, d_c, y_c);
-            V[i] = x;
-            r_c = r_n;
-            e_c = e_n;
-            d_c = d_n;
-            y_c = y_n;
+    for (int i = b.b0 + 1; i <= b.b1; i += kBlk) {
+        const double *pg = D + i, *ph = R + i, *pe = Eo + i;
+        double *pv = V + i;
+        double g[kBlk], h[kBlk], e[kBlk], y[kBlk];
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            g[j] = pg[j];
+            h[j] = ph[j];
+            if constexpr (!kFast) {
+                e[j] = pe[j];
+                y[j] = pv[j];
+            }
+        }
+        const int nv = b.b1 - i + 1;
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            if constexpr (kFast)
+                x = __builtin_fma(-g[j], x, h[j]);
+            else
+                x = div_rn(h[j] - e[j] * x, g[j], y[j]);
+            if (j < nv) pv[j] = x;
         }
     }
 }
@@ -458,7 +545,7 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
 // In the sweeps the branches of a level go to consecutive lanes (sorted by
 // length on the host), so one wave instruction advances as many chains as
 // the level has branches.
-template <typename T>
+template <typename T, bool kFast>
 __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
                                          char *base, int64_t epoch, int pid) {
     const int tid = threadIdx.x;
@@ -554,16 +641,21 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         MMH_PHASE(2);
 
         // ---- C: backward sweep by height -----------------------------------
+        // (V^n is no longer needed: detection keeps its own copy, so the V
+        // slot holds the reciprocal pivots, or Q of the fast solver)
         for (int h = 0; h < pk.nbw; ++h) {
             for (int q2 = lvl[h] + slot; q2 < lvl[h + 1]; q2 += NT) {
                 const int bid = sched[q2];
-                sweep_back(D, R, Eo, br[bid], bid, chl, tb.CD, tb.CR);
+                sweep_back_blk<kFast>(D, R, V, Eo, br[bid], bid, chl, tb.CD, tb.CR);
             }
             __syncthreads();
         }
-        // reciprocals of the finished diagonal, in parallel (V^n is no longer
-        // needed: detection keeps its own copy)
-        for (int i = tid; i < n; i += NT) V[i] = div_nr(1.0, D[i]);
+        for (int i = tid; i < n; i += NT) {
+            if constexpr (kFast)
+                pivots_h(D, R, V, Eo, i);
+            else
+                V[i] = div_nr(1.0, D[i]);
+        }
         __syncthreads();
         MMH_PHASE(3);
 
@@ -571,8 +663,9 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         const int32_t *flv = lvl + pk.nbw + 1;
         const uint16_t *fsc = sched + pk.nbr;
         for (int h = 0; h < pk.nfw; ++h) {
-            for (int q2 = flv[h] + slot; q2 < flv[h + 1]; q2 += NT)
-                sweep_fwd(V, D, R, Eo, br[fsc[q2]]);
+            for (int q2 = flv[h] + slot; q2 < flv[h + 1]; q2 += NT) {
+                sweep_fwd_blk<kFast>(V, D, R, Eo, br[fsc[q2]]);
+            }
             __syncthreads();
         }
         MMH_PHASE(4);
@@ -613,7 +706,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     MMH_PHASE(6);
 }
 
-template <typename T>
+template <typename T, bool kFast>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
     k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
@@ -624,9 +717,15 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         const PackDesc pk = a.packs[pid];
         uint64_t tstart = 0;
         if (a.pack_time && threadIdx.x == 0) tstart = wall_clock64();
-        char *base = pk.global_mem ? a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride
-                                   : smem + pk.tbytes;
-        run_pack<T>(a, pk, smem, base, epoch, pid);
+        // two call sites, so that in the common one the state pointer is
+        // visibly derived from the shared array and its accesses compile to
+        // LDS instructions rather than generic (flat) ones
+        if (pk.global_mem)
+            run_pack<T, kFast>(a, pk, smem,
+                               a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch,
+                               pid);
+        else
+            run_pack<T, kFast>(a, pk, smem, smem + pk.tbytes, epoch, pid);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
@@ -663,21 +762,32 @@ hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_epoch(const EpochArgs &a, int precision, int n_wg, int threads,
+hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg, int threads,
                         size_t lds_bytes, hipStream_t s) {
-    if (precision == 0)
-        hipLaunchKernelGGL(k_epoch<double>, dim3(n_wg), dim3(threads), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL(k_epoch<float>, dim3(n_wg), dim3(threads), lds_bytes, s, a);
+    const dim3 g(n_wg), b(threads);
+    if (precision == 0) {
+        if (solver == 0)
+            hipLaunchKernelGGL((k_epoch<double, false>), g, b, lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((k_epoch<double, true>), g, b, lds_bytes, s, a);
+    } else {
+        if (solver == 0)
+            hipLaunchKernelGGL((k_epoch<float, false>), g, b, lds_bytes, s, a);
+        else
+            hipLaunchKernelGGL((k_epoch<float, true>), g, b, lds_bytes, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t set_epoch_lds_limit(int bytes) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_epoch<double>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)k_epoch<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fns[] = {(const void *)k_epoch<double, false>, (const void *)k_epoch<double, true>,
+                         (const void *)k_epoch<float, false>, (const void *)k_epoch<float, true>};
+    for (const void *f : fns) {
+        const hipError_t e =
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #ifdef MMH_PHASE_PROFILE

@@ -17,6 +17,7 @@ LIB_PATH = os.environ.get("MMHINES_LIB") or os.path.join(HERE, "libmmhines.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
 FP64, FP32_GATING = 0, 1
+SOLVE_EXACT, SOLVE_FAST = 0, 1
 PACK_PLAIN, PACK_COUNT, PACK_LEARNED = 0, 1, 2
 SCHED_AUTO, SCHED_PERSISTENT, SCHED_DISPATCH = 0, 1, 2
 N_FEATURES = 16
@@ -41,7 +42,8 @@ class Params(C.Structure):
     _fields_ = [
         ("dt_ms", C.c_double), ("theta", C.c_double), ("tau_syn_ms", C.c_double),
         ("e_syn_mV", C.c_double), ("v_thresh_mV", C.c_double), ("v_init_mV", C.c_double),
-        ("precision", C.c_int32), ("packing", C.c_int32), ("sched", C.c_int32),
+        ("precision", C.c_int32), ("solver", C.c_int32), ("packing", C.c_int32),
+        ("sched", C.c_int32),
         ("epoch_steps", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
         ("pack_comps", C.c_int32), ("lds_comps", C.c_int32), ("use_graph", C.c_int32),
         ("record_timings", C.c_int32), ("cost_model", C.c_void_p), ("hip_stream", C.c_void_p),
@@ -144,7 +146,7 @@ class Simulation:
                  sched: int = SCHED_AUTO, autotune: bool = False, threads: int = 0,
                  pack_comps: int = 0, lds_comps: int = 0, use_graph: bool = True,
                  record_timings: bool = False, cost_model: np.ndarray | None = None,
-                 epoch_steps: int = 0, stream: int | None = None):
+                 epoch_steps: int = 0, stream: int | None = None, solver: int | None = None):
         L = lib()
         pr = prob["params"]
         ch = prob["channels"]
@@ -152,6 +154,8 @@ class Simulation:
         P.dt_ms, P.theta, P.tau_syn_ms = pr["dt"], pr["theta"], pr["tau_syn"]
         P.e_syn_mV, P.v_thresh_mV, P.v_init_mV = pr["e_syn"], pr["v_thresh"], pr["v_init"]
         P.precision = int(pr["precision"] if precision is None else precision)
+        if solver is not None:
+            P.solver = int(solver)
         P.packing, P.sched, P.autotune = packing, sched, int(autotune)
         P.threads, P.pack_comps, P.lds_comps = threads, pack_comps, lds_comps
         P.use_graph, P.record_timings, P.epoch_steps = int(use_graph), int(record_timings), epoch_steps
