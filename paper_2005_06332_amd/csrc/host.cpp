@@ -243,8 +243,9 @@ struct sim {
     DBuf<double> d_V, d_cdt, d_e, d_len, d_diam, d_w64, d_iext64, d_q;
     DBuf<char> d_gm, d_gh, d_gn, d_af, d_sg, d_sw, d_niext, d_scratch;
     DBuf<uint32_t> d_topo;
-    DBuf<uint16_t> d_scomp, d_sseg, d_chl, d_sched;
+    DBuf<uint16_t> d_scomp, d_sseg, d_chl;
     DBuf<Branch> d_br;
+    DBuf<FwBranch> d_fw;
     DBuf<int64_t> d_ncomp0, d_epoch;
     DBuf<uint64_t> d_hist, d_ptime;
     int64_t hist_epochs = 0;
@@ -479,8 +480,11 @@ void build_layout(sim_t *s, Variant v) {
     std::vector<double> len, dia, w64, iext64;
     std::vector<int64_t> ncomp0;
     std::vector<int32_t> spre, sdel;
-    std::vector<uint16_t> scomp, sseg, chl, sched;
+    std::vector<uint16_t> scomp, sseg, chl;
     std::vector<Branch> brs;
+    std::vector<FwBranch> fws;
+    // per-pack branch scratch (pack-local branch index = br_base + local)
+    std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0, cslot;
     topo.reserve(s->C);
     lparent.reserve(s->C);
     len.reserve(s->C);
@@ -513,7 +517,11 @@ void build_layout(sim_t *s, Variant v) {
         d.nbr = pk[p].nbr;
         d.ch0 = (int32_t)chl.size();
         d.lv0 = (int32_t)lvl.size();
-        d.sc0 = (int32_t)sched.size();
+        tb0.clear();
+        tb1.clear();
+        tpar.clear();
+        tch.clear();
+        tch_off.assign(1, 0);
         int32_t maxh = 0, maxd = 0;
         int32_t comp_base = 0, br_base = 0;
         segs.clear();
@@ -543,16 +551,12 @@ void build_layout(sim_t *s, Variant v) {
                 s->comp_perm.push_back(b + i);
             }
             for (int32_t bb = 0; bb < nb; ++bb) {
-                Branch r;
-                r.b0 = (uint16_t)(comp_base + t.b0[bb]);
-                r.b1 = (uint16_t)(comp_base + t.b1[bb]);
-                r.child0 = (uint16_t)(chl.size() - d.ch0);
-                r.nchild = (uint16_t)(t.child_off[bb + 1] - t.child_off[bb]);
-                r.par = bb == 0 ? kRootPar : (uint16_t)(comp_base + s->parent[b + t.b0[bb]]);
-                r.pad = 0;
+                tb0.push_back(comp_base + t.b0[bb]);
+                tb1.push_back(comp_base + t.b1[bb]);
+                tpar.push_back(bb == 0 ? (int32_t)kRootPar : comp_base + s->parent[b + t.b0[bb]]);
                 for (int32_t c = t.child_off[bb]; c < t.child_off[bb + 1]; ++c)
-                    chl.push_back((uint16_t)(br_base + t.child[c]));
-                brs.push_back(r);
+                    tch.push_back(br_base + t.child[c]);
+                tch_off.push_back((int32_t)tch.size());
                 bh.push_back(t.height[bb]);
                 bd.push_back(t.depth[bb]);
             }
@@ -567,8 +571,9 @@ void build_layout(sim_t *s, Variant v) {
             comp_base += n;
             br_base += nb;
         }
-        if (d.ch0 + (int64_t)(chl.size() - d.ch0) > INT32_MAX) throw fail(SIM_ENOMEM, "child list too large");
-        if ((int64_t)chl.size() - d.ch0 > 65535) throw fail(SIM_EINVAL, "pack child list too large");
+        if ((int64_t)chl.size() + (int64_t)tch.size() > INT32_MAX)
+            throw fail(SIM_ENOMEM, "child list too large");
+        if (tch.size() > 65535) throw fail(SIM_EINVAL, "pack child list too large");
         // synapses by (local compartment, id)
         std::sort(segs.begin(), segs.end());
         for (size_t u = 0; u < segs.size(); ++u) {
@@ -587,18 +592,19 @@ void build_layout(sim_t *s, Variant v) {
             if (run > 65535) throw fail(SIM_EINVAL, "too many synapses on one compartment");
             sseg.push_back((uint16_t)run);
         }
-        // levels: branches by height (backward), by depth (forward)
+        // levels: branches by height (backward), by depth (forward); within a
+        // level, longest chains first so that the lanes of a wave finish
+        // together. The backward order is also the order of the branch
+        // records (a branch's id is its position).
         d.nbw = maxh + 1;
         d.nfw = maxd + 1;
         const int32_t nbr = d.nbr;
-        std::vector<int32_t> cnt(std::max(d.nbw, d.nfw) + 1, 0);
-        // within a level, longest chains first so that the lanes of a wave
-        // finish together
+        auto nchild = [&](int32_t bb) { return tch_off[bb + 1] - tch_off[bb]; };
         auto chain_len = [&](int32_t bb, bool with_children) {
-            const Branch &r = brs[d.br0 + bb];
-            return (int)(r.b1 - r.b0) + (with_children ? (int)r.nchild : 0);
+            return (tb1[bb] - tb0[bb]) + (with_children ? nchild(bb) : 0);
         };
-        std::vector<int32_t> lev;
+        std::vector<int32_t> lev, order;
+        order.clear();
         lvl.push_back(0);
         for (int h = 0; h < d.nbw; ++h) {
             lev.clear();
@@ -607,8 +613,43 @@ void build_layout(sim_t *s, Variant v) {
             std::stable_sort(lev.begin(), lev.end(), [&](int32_t x, int32_t y) {
                 return chain_len(x, true) > chain_len(y, true);
             });
-            for (int32_t bb : lev) sched.push_back((uint16_t)bb);
-            lvl.push_back((int32_t)(sched.size() - d.sc0));
+            order.insert(order.end(), lev.begin(), lev.end());
+            lvl.push_back((int32_t)order.size());
+        }
+        pos.assign(nbr, 0);
+        for (int32_t k = 0; k < nbr; ++k) pos[order[k]] = k;
+        // child entries in record order; each child's slot among its siblings
+        child0.assign(nbr, 0);
+        cslot.assign(nbr, 0xFFFF);
+        {
+            int32_t acc = 0;
+            for (int32_t k = 0; k < nbr; ++k) {
+                const int32_t bb = order[k];
+                child0[k] = acc;
+                for (int32_t r = 0; r < nchild(bb); ++r) {
+                    const int32_t c = tch[tch_off[bb] + r];
+                    chl.push_back((uint16_t)tb0[c]);
+                    cslot[c] = acc + r;
+                }
+                acc += nchild(bb);
+            }
+        }
+        for (int32_t k = 0; k < nbr; ++k) {
+            const int32_t bb = order[k];
+            Branch r{};
+            r.b0 = (uint16_t)tb0[bb];
+            r.b1 = (uint16_t)tb1[bb];
+            r.child0 = (uint16_t)child0[k];
+            r.nchild = (uint16_t)nchild(bb);
+            r.par = (uint16_t)tpar[bb];
+            r.cslot = (uint16_t)cslot[bb];
+            brs.push_back(r);
+        }
+        // branch ids in the compartment words: positions in record order
+        for (int64_t c = d.comp0; c < (int64_t)topo.size(); ++c) {
+            const uint32_t w = topo[c];
+            const uint32_t bid = (w >> 16) & 0x7FFFu;
+            if (bid != kNone) topo[c] = (w & ~(0x7FFFu << 16)) | ((uint32_t)pos[bid] << 16);
         }
         lvl.push_back(0);
         for (int h = 0; h < d.nfw; ++h) {
@@ -618,8 +659,9 @@ void build_layout(sim_t *s, Variant v) {
             std::stable_sort(lev.begin(), lev.end(), [&](int32_t x, int32_t y) {
                 return chain_len(x, false) > chain_len(y, false);
             });
-            for (int32_t bb : lev) sched.push_back((uint16_t)bb);
-            lvl.push_back((int32_t)(sched.size() - d.sc0 - nbr));
+            for (int32_t bb : lev)
+                fws.push_back(FwBranch{(uint16_t)tb0[bb], (uint16_t)tb1[bb], (uint16_t)tpar[bb], 0});
+            lvl.push_back((int32_t)(fws.size() - d.br0));
         }
         d.nch = (int32_t)chl.size() - d.ch0;
         d.tbytes = (int32_t)(s->tsize == 8
@@ -721,9 +763,9 @@ void build_layout(sim_t *s, Variant v) {
     s->d_scomp.upload(scomp);
     s->d_sseg.upload(sseg);
     s->d_br.upload(brs);
+    s->d_fw.upload(fws);
     s->d_chl.upload(chl);
     s->d_lvl.upload(lvl);
-    s->d_sched.upload(sched);
     const int64_t C = s->C, S = s->S;
     s->d_V.alloc(C);
     s->d_cdt.alloc(C);
@@ -822,9 +864,9 @@ EpochArgs make_args(sim_t *s) {
     a.ndet = s->d_ndet.p;
     a.niext = s->d_niext.p;
     a.br = s->d_br.p;
+    a.fw = s->d_fw.p;
     a.chl = s->d_chl.p;
     a.lvl = s->d_lvl.p;
-    a.sched = s->d_sched.p;
     a.hist = s->d_hist.p;
     a.n_neurons = s->N;
     a.E = s->E;
@@ -1299,7 +1341,7 @@ void sim_destroy(sim_t *s) {
     fr(s->d_e); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
     fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
     fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
-    fr(s->d_sseg); fr(s->d_chl); fr(s->d_sched); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
+    fr(s->d_sseg); fr(s->d_chl); fr(s->d_fw); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
     fr(s->d_hist); fr(s->d_ptime);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     for (int c = 1; c < kClasses; ++c) {

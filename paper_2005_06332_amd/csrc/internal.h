@@ -30,13 +30,21 @@ __host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh
 }
 
 // A branch: a maximal run b0..b1 of consecutive compartments where each one
-// is the only child of the previous. Its children (branches whose base hangs
-// off b1) are listed by branch id, in ascending order of their bases, at
-// child list entries child0 .. child0+nchild-1. par is the parent
-// compartment of b0, or kRootPar when b0 is the root of its neuron.
+// is the only child of the previous. Branch records of a pack are stored in
+// backward-sweep order (by height, longest chains first within a level), and
+// a branch's id is its position there. Its children (branches whose base
+// hangs off b1) occupy child entries child0 .. child0+nchild-1 in ascending
+// order of their bases: the child list holds their base compartments, and
+// the child contributions of the elimination live at the same entries (a
+// child leaves its own at entry cslot). par is the parent compartment of b0,
+// or kRootPar when b0 is the root of its neuron (then cslot is unused).
 constexpr uint16_t kRootPar = 0xFFFF;
-struct Branch {
-    uint16_t b0, b1, child0, nchild, par, pad;
+struct alignas(16) Branch {
+    uint16_t b0, b1, child0, nchild, par, cslot, pad0, pad1;
+};
+// Forward-sweep record (by depth, longest chains first within a level).
+struct alignas(8) FwBranch {
+    uint16_t b0, b1, par, pad;
 };
 
 struct PackDesc {
@@ -44,11 +52,10 @@ struct PackDesc {
     int64_t syn0;    // first synapse (packed index)
     int32_t ncomp, nsyn;
     int32_t neur0, nneur;  // packed neuron range
-    int32_t br0, nbr;      // branch table range
-    int32_t ch0;           // child list offset
+    int32_t br0, nbr;      // branch table range (backward and forward records)
+    int32_t ch0;           // child list / child contribution offset
     int32_t lv0;           // level offsets: nbw+1 backward then nfw+1 forward
     int32_t nbw, nfw;      // number of height / depth levels
-    int32_t sc0;           // schedule: nbr ids by height, then nbr by depth
     int32_t global_mem;    // 0: state in LDS; k > 0: state in global scratch slice k-1
     int32_t nch;           // child list entries
     int32_t tbytes;        // bytes of staged tables (always in LDS)
@@ -79,9 +86,9 @@ struct EpochArgs {
     const void *niext;        // injected current (T)
     // per pack tables
     const Branch *br;
+    const FwBranch *fw;
     const uint16_t *chl;
     const int32_t *lvl;
-    const uint16_t *sched;
     // spike history: hist[epoch * n_neurons + input id] = bit t set when the
     // neuron spiked at step epoch*E + t + 1
     uint64_t *hist;
@@ -112,16 +119,17 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
     b += 64;  // slack: the blocked sweeps read up to 3 doubles past a branch
     return b;
 }
-// Bytes of the pack's tables staged in LDS next to the state: per-branch
-// child contributions (2 doubles), synapse weights (T), level offsets, branch
-// records, child lists, schedule (two orders), synapse targets and run
+// Bytes of the pack's tables staged in LDS next to the state: backward and
+// forward branch records, child contributions (2 doubles per child entry),
+// synapse weights (T), level offsets, child list, synapse targets and run
 // lengths. Must match the carve-up in the kernel.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn) {
-    int64_t b = 16 * nbr + (int64_t)sizeof(T) * nsyn;
+    int64_t b = (int64_t)sizeof(Branch) * nbr + (int64_t)sizeof(FwBranch) * nbr;
+    b += 16 * nch + (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
-    b += (int64_t)sizeof(Branch) * nbr + 2 * nch + 2 * 2 * nbr + 2 * 2 * nsyn;
+    b += 2 * nch + 2 * 2 * nsyn;
     return (b + 15) / 16 * 16;
 }
 

@@ -330,13 +330,11 @@ template <bool kFast>
 __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *__restrict__ R,
                                                double *__restrict__ Q,
                                                const double *__restrict__ Eo, const Branch b,
-                                               const int bid, const uint16_t *__restrict__ chl,
                                                double *__restrict__ CD, double *__restrict__ CR) {
     double P = D[b.b1], S = R[b.b1];
     for (int c = b.nchild - 1; c >= 0; --c) {
-        const int cid = chl[b.child0 + c];
-        P = P - CD[cid];
-        S = S - CR[cid];
+        P = P - CD[b.child0 + c];
+        S = S - CR[b.child0 + c];
     }
     double q = 1.0;
     D[b.b1] = P;
@@ -384,12 +382,12 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
         const double P0 = D[b.b0], S0 = R[b.b0];
         if constexpr (kFast) {
             const double y = rcp_nr(P0);
-            CD[bid] = ((e0 * e0) * Q[b.b0]) * y;
-            CR[bid] = (e0 * S0) * y;
+            CD[b.cslot] = ((e0 * e0) * Q[b.b0]) * y;
+            CR[b.cslot] = (e0 * S0) * y;
         } else {
             const double f = div_nr(e0, P0);
-            CD[bid] = f * e0;
-            CR[bid] = f * S0;
+            CD[b.cslot] = f * e0;
+            CR[b.cslot] = f * S0;
         }
     }
 }
@@ -401,7 +399,7 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
 template <bool kFast>
 __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const double *__restrict__ D,
                                               const double *__restrict__ R,
-                                              const double *__restrict__ Eo, const Branch b) {
+                                              const double *__restrict__ Eo, const FwBranch b) {
     double x;
     if constexpr (kFast) {
         x = R[b.b0];
@@ -488,7 +486,7 @@ __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const d
     } else {
         const Branch b = br[bid];
         for (int q = 0; q < b.nchild; ++q) {
-            const int j = br[chl[b.child0 + q]].b0;
+            const int j = chl[b.child0 + q];
             const double ej = Eo[j];
             ax = ax - (ej * c.ginv) * (v - V[j]);
             d = d - ej;
@@ -508,32 +506,33 @@ __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x,
     x = gate_step<T>(x, an, bn, dt);
 }
 
-// The pack's tables, staged in LDS for the whole epoch: per-branch child
-// contributions (CD, CR), synapse weights, branch records, child lists,
-// schedule, level offsets, synapse targets and run lengths. The layout must
+// The pack's tables, staged in LDS for the whole epoch: backward and forward
+// branch records, child contributions (CD, CR), synapse weights, level
+// offsets, child list, synapse targets and run lengths. The layout must
 // match pack_table_bytes().
 template <typename T>
 struct Tables {
+    Branch *br;
+    FwBranch *fw;
     double *CD, *CR;
     T *sw;
-    Branch *br;
-    uint16_t *chl, *sched, *scomp, *sseg;
     int32_t *lvl;
+    uint16_t *chl, *scomp, *sseg;
 };
 
 template <typename T>
 __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk) {
     Tables<T> t;
-    t.CD = (double *)smem;
-    t.CR = t.CD + pk.nbr;
-    t.sw = (T *)(t.CR + pk.nbr);
+    t.br = (Branch *)smem;
+    t.fw = (FwBranch *)(t.br + pk.nbr);
+    t.CD = (double *)(t.fw + pk.nbr);
+    t.CR = t.CD + pk.nch;
+    t.sw = (T *)(t.CR + pk.nch);
     char *p = (char *)(t.sw + pk.nsyn);
     p = smem + (((p - smem) + 3) / 4) * 4;
     t.lvl = (int32_t *)p;
-    t.br = (Branch *)(t.lvl + pk.nbw + pk.nfw + 2);
-    t.chl = (uint16_t *)(t.br + pk.nbr);
-    t.sched = t.chl + pk.nch;
-    t.scomp = t.sched + 2 * pk.nbr;
+    t.chl = (uint16_t *)(t.lvl + pk.nbw + pk.nfw + 2);
+    t.scomp = t.chl + pk.nch;
     t.sseg = t.scomp + pk.nsyn;
     return t;
 }
@@ -560,11 +559,13 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 #endif
     {
         const Branch *gbr = a.br + pk.br0;
-        for (int k = tid; k < pk.nbr; k += NT) tb.br[k] = gbr[k];
+        const FwBranch *gfw = a.fw + pk.br0;
+        for (int k = tid; k < pk.nbr; k += NT) {
+            tb.br[k] = gbr[k];
+            tb.fw[k] = gfw[k];
+        }
         const uint16_t *gch = a.chl + pk.ch0;
         for (int k = tid; k < pk.nch; k += NT) tb.chl[k] = gch[k];
-        const uint16_t *gsc = a.sched + pk.sc0;
-        for (int k = tid; k < 2 * pk.nbr; k += NT) tb.sched[k] = gsc[k];
         const int32_t *glv = a.lvl + pk.lv0;
         for (int k = tid; k < pk.nbw + pk.nfw + 2; k += NT) tb.lvl[k] = glv[k];
         const T *gsw = (const T *)a.sw + s0;
@@ -588,7 +589,6 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const Branch *br = tb.br;
     const uint16_t *chl = tb.chl;
     const int32_t *lvl = tb.lvl;
-    const uint16_t *sched = tb.sched;
 
     const T gnabar = (T)a.gnabar, gkbar = (T)a.gkbar, gl = (T)a.gl;
     const T ena = (T)a.ena, ek = (T)a.ek, el = (T)a.el;
@@ -642,13 +642,24 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 
         // ---- C: backward sweep by height -----------------------------------
         // (V^n is no longer needed: detection keeps its own copy, so the V
-        // slot holds the reciprocal pivots, or Q of the fast solver)
-        for (int h = 0; h < pk.nbw; ++h) {
-            for (int q2 = lvl[h] + slot; q2 < lvl[h + 1]; q2 += NT) {
-                const int bid = sched[q2];
-                sweep_back_blk<kFast>(D, R, V, Eo, br[bid], bid, chl, tb.CD, tb.CR);
+        // slot holds the reciprocal pivots, or Q of the fast solver). Each
+        // lane takes entry `slot` of a level; the next level's bounds and
+        // record are read before the current level's chains run, so their
+        // latency is hidden (the tables are constant).
+        {
+            int lo = lvl[0], hi = lvl[1];
+            Branch cur = br[min(lo + slot, pk.nbr - 1)];
+            for (int h = 0; h < pk.nbw; ++h) {
+                const int hi2 = lvl[min(h + 2, pk.nbw)];
+                const Branch nxt = br[min(hi + slot, pk.nbr - 1)];
+                if (lo + slot < hi) sweep_back_blk<kFast>(D, R, V, Eo, cur, tb.CD, tb.CR);
+                for (int q2 = lo + slot + NT; q2 < hi; q2 += NT)
+                    sweep_back_blk<kFast>(D, R, V, Eo, br[q2], tb.CD, tb.CR);
+                __syncthreads();
+                cur = nxt;
+                lo = hi;
+                hi = hi2;
             }
-            __syncthreads();
         }
         for (int i = tid; i < n; i += NT) {
             if constexpr (kFast)
@@ -660,13 +671,22 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         MMH_PHASE(3);
 
         // ---- D: forward sweep by depth -------------------------------------
-        const int32_t *flv = lvl + pk.nbw + 1;
-        const uint16_t *fsc = sched + pk.nbr;
-        for (int h = 0; h < pk.nfw; ++h) {
-            for (int q2 = flv[h] + slot; q2 < flv[h + 1]; q2 += NT) {
-                sweep_fwd_blk<kFast>(V, D, R, Eo, br[fsc[q2]]);
+        {
+            const int32_t *flv = lvl + pk.nbw + 1;
+            const FwBranch *fw = tb.fw;
+            int lo = flv[0], hi = flv[1];
+            FwBranch cur = fw[min(lo + slot, pk.nbr - 1)];
+            for (int h = 0; h < pk.nfw; ++h) {
+                const int hi2 = flv[min(h + 2, pk.nfw)];
+                const FwBranch nxt = fw[min(hi + slot, pk.nbr - 1)];
+                if (lo + slot < hi) sweep_fwd_blk<kFast>(V, D, R, Eo, cur);
+                for (int q2 = lo + slot + NT; q2 < hi; q2 += NT)
+                    sweep_fwd_blk<kFast>(V, D, R, Eo, fw[q2]);
+                __syncthreads();
+                cur = nxt;
+                lo = hi;
+                hi = hi2;
             }
-            __syncthreads();
         }
         MMH_PHASE(4);
 
