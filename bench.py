@@ -78,16 +78,20 @@ def describe(prob: dict) -> str:
             f"dt {prob['params']['dt']} ms")
 
 
-def time_run(S, prob, steps, warmup, packing, cost_model=None, autotune=True, stream=None):
+def time_run(S, prob, steps, warmup, packing, cost_model=None, autotune=True, stream=None,
+             solver=1):
     import torch
     g = S.Simulation(prob, packing=packing, autotune=autotune, cost_model=cost_model,
-                     stream=stream.cuda_stream if stream is not None else None)
+                     stream=stream.cuda_stream if stream is not None else None, solver=solver)
     torch.cuda.synchronize()
     if warmup:
         g.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # launch timing on: every epoch is launched directly and each size-class
+    # launch is bracketed by HIP events on the stream it runs on
+    g.set_kernel_timing(True)
     with torch.cuda.stream(stream):
         ev0.record(stream)
         g.step(steps)
@@ -139,6 +143,9 @@ def main():
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--neurons", type=int, default=0)
     ap.add_argument("--packing", default="count", choices=["plain", "count", "learned"])
+    ap.add_argument("--solver", default="fast", choices=["exact", "fast"],
+                    help="exact: the elimination in the reference operation order (bitwise "
+                         "equal to the CPU oracle); fast: division-free homogeneous form")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-packing comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
@@ -168,12 +175,15 @@ def main():
     if packing == S.PACK_LEARNED:
         cost_model = costmodel.load_or_train(prob)
 
+    solver = S.SOLVE_FAST if args.solver == "fast" else S.SOLVE_EXACT
     g, ms = time_run(S, prob, args.steps, args.warmup, packing, cost_model,
-                     autotune=not args.no_autotune, stream=stream)
+                     autotune=not args.no_autotune, stream=stream, solver=solver)
     config_str = g.config
-    # kernel time per launch: epoch launches in the timed region
     E = int(config_str.split("E=")[1].split()[0])
-    launches = args.steps // E + (1 if args.steps % E else 0)
+    # the dominant kernel: the launch of size class 0 (most packs), timed
+    # with HIP events on its own stream over the timed region
+    cls = [g.class_time(c) for c in range(3)]
+    epoch_ms, epochs = g.kernel_time()
     g.close()
     upd = float(C) * args.steps
     value = upd / (ms / 1e3)
@@ -188,14 +198,15 @@ def main():
     plain = None
     if not args.no_plain and packing != S.PACK_PLAIN:
         gp, msp = time_run(S, prob, args.steps, args.warmup, S.PACK_PLAIN, autotune=False,
-                           stream=stream)
+                           stream=stream, solver=solver)
         gp.close()
         plain = upd / (msp / 1e3)
 
     syn_per_comp = prob["syn_pre"].shape[0] / C
     b_alg = bytes_per_update(prec, multi, syn_per_comp)
-    kernel_ms = ms / launches
-    upd_per_launch = upd / launches
+    k_ms, k_n, k_comps = cls[0]
+    kernel_ms = k_ms / max(k_n, 1)
+    upd_per_launch = float(k_comps) * E
     achieved_gbs = b_alg * upd_per_launch / (kernel_ms / 1e3) / 1e9
     flops = flops_per_update(prec)
     achieved_tf = flops * upd_per_launch / (kernel_ms / 1e3) / 1e12
@@ -228,7 +239,7 @@ def main():
             "workload": describe(prob),
             "neurons": N, "compartments": C, "synapses": int(prob["syn_pre"].shape[0]),
             "precision": "fp32-gating/fp64-hines" if prec == 1 else "fp64",
-            "packing": args.packing, "launch": config_str,
+            "packing": args.packing, "solver": args.solver, "launch": config_str,
             "plain_packing_value": plain,
             "speedup_vs_plain_packing": (value / plain) if plain else None,
             "hbm_roofline_frac_streaming": value * b_alg / (PEAK_HBM_GBS * 1e9),
@@ -240,7 +251,14 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tf / PEAK_VALU_TFLOPS,
             "traffic": traffic,
+            "kernel": "k_epoch, size class 0 launch",
             "kernel_ms": kernel_ms,
+            "kernel_launches": k_n,
+            "compartments_per_launch_step": k_comps,
+            "updates_per_launch": upd_per_launch,
+            "epoch_ms": epoch_ms / max(epochs, 1),
+            "class_ms": [c[0] / max(c[1], 1) for c in cls],
+            "class_compartments": [c[2] for c in cls],
             "flops_per_update": flops,
             "streaming_bytes_per_update": b_alg,
             "streaming_hbm_GBps": achieved_gbs,

@@ -169,6 +169,7 @@ struct Variant {
     int pack_comps = 1024;
     int lds_limit = 64 * 1024;  // bytes of LDS per workgroup
     int sched = SIM_SCHED_PERSISTENT;
+    int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
 };
 
 template <typename X>
@@ -259,6 +260,13 @@ struct sim {
     bool kt_on = false;
     double kt_ms = 0;
     int64_t kt_launches = 0;
+    // launch timing: event pairs (epoch span, then one per size class) taken
+    // from pools, read back once per sim_step
+    std::vector<hipEvent_t> kt_pool[kClasses + 1];
+    int kt_used[kClasses + 1] = {};
+    double kt_cls_ms[kClasses] = {};
+    int64_t kt_cls_n[kClasses] = {};
+    int64_t cls_comps[kClasses] = {};  // compartments of each size class
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double tick_ns = 10.0;
 
@@ -688,6 +696,9 @@ void build_layout(sim_t *s, Variant v) {
     ncomp0.push_back((int64_t)topo.size());
     s->scratch_bytes = scratch;
 
+    for (int c = 0; c < kClasses; ++c) s->cls_comps[c] = 0;
+    for (int p = 0; p < npk; ++p) s->cls_comps[pclass[p]] += s->packs[p].ncomp;
+
     // workgroup lists, one per size class
     s->wg_off.clear();
     s->wg_list.clear();
@@ -914,6 +925,37 @@ void assign_scratch(sim_t *s) {
     }
 }
 
+// Two events of pool k for one timed launch (created on first use).
+std::pair<hipEvent_t, hipEvent_t> kt_pair(sim_t *s, int k) {
+    auto &pool = s->kt_pool[k];
+    int &u = s->kt_used[k];
+    while ((int)pool.size() < u + 2) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        pool.push_back(e);
+    }
+    u += 2;
+    return {pool[u - 2], pool[u - 1]};
+}
+
+// Read back and reset the event pairs recorded since the last call.
+void kt_collect(sim_t *s) {
+    for (int k = 0; k <= kClasses; ++k) {
+        for (int u = 0; u + 1 < s->kt_used[k]; u += 2) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, s->kt_pool[k][u], s->kt_pool[k][u + 1]));
+            if (k == 0) {
+                s->kt_ms += ms;
+                s->kt_launches++;
+            } else {
+                s->kt_cls_ms[k - 1] += ms;
+                s->kt_cls_n[k - 1]++;
+            }
+        }
+        s->kt_used[k] = 0;
+    }
+}
+
 // One epoch (or part of one): the large-pack class on the second stream and
 // the small-pack class on the main stream run concurrently, forked from and
 // joined back into the main stream (also inside a captured graph).
@@ -928,6 +970,7 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         a.t0 = t0;
         a.t1 = t1;
         a.scratch_stride = s->scratch_bytes;
+        a.prio = 0;
         return a;
     };
     bool forked = false;
@@ -939,12 +982,27 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
             forked = true;
         }
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
-        HIPCHK(launch_epoch(args(L), pr, s->solver, L.n_wg, s->var.threads, L.lds, s->side[c]));
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (s->kt_on) {
+            ev = kt_pair(s, c + 1);
+            HIPCHK(hipEventRecord(ev.first, s->side[c]));
+        }
+        EpochArgs ac = args(L);
+        ac.prio = std::min(3, c * s->var.prio);
+        HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, s->var.threads, L.lds, s->side[c]));
+        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
     const Launch &S0 = s->launch[0];
-    if (S0.n_wg > 0)
+    if (S0.n_wg > 0) {
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (s->kt_on) {
+            ev = kt_pair(s, 1);
+            HIPCHK(hipEventRecord(ev.first, s->stream));
+        }
         HIPCHK(launch_epoch(args(S0), pr, s->solver, S0.n_wg, s->var.threads, S0.lds, s->stream));
+        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
+    }
     for (int c = 1; c < kClasses; ++c)
         if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
 }
@@ -990,20 +1048,18 @@ void run_steps(sim_t *s, int64_t n) {
             continue;
         }
         const int t1 = (int)std::min<int64_t>(E, t0 + n);
-        if (s->kt_on) HIPCHK(hipEventRecord(s->ev0, s->stream));
-        launch_range(s, ep, t0, t1, false);
+        std::pair<hipEvent_t, hipEvent_t> ev{};
         if (s->kt_on) {
-            HIPCHK(hipEventRecord(s->ev1, s->stream));
-            HIPCHK(hipEventSynchronize(s->ev1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-            s->kt_ms += ms;
-            s->kt_launches++;
+            ev = kt_pair(s, 0);
+            HIPCHK(hipEventRecord(ev.first, s->stream));
         }
+        launch_range(s, ep, t0, t1, false);
+        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
         s->step += t1 - t0;
         n -= t1 - t0;
     }
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->kt_on) kt_collect(s);
 }
 
 std::string describe(const sim_t *s) {
@@ -1320,6 +1376,18 @@ int sim_set_kernel_timing(sim_t *s, int32_t on) {
     s->kt_on = on != 0;
     s->kt_ms = 0;
     s->kt_launches = 0;
+    for (int c = 0; c < kClasses; ++c) {
+        s->kt_cls_ms[c] = 0;
+        s->kt_cls_n[c] = 0;
+    }
+    return SIM_OK;
+}
+
+int sim_class_time(sim_t *s, int32_t cls, double *ms, int64_t *launches, int64_t *comps) {
+    if (!s || cls < 0 || cls >= kClasses) return SIM_EINVAL;
+    if (ms) *ms = s->kt_cls_ms[cls];
+    if (launches) *launches = s->kt_cls_n[cls];
+    if (comps) *comps = s->cls_comps[cls];
     return SIM_OK;
 }
 
@@ -1348,6 +1416,8 @@ void sim_destroy(sim_t *s) {
         if (s->ev_join[c]) (void)hipEventDestroy(s->ev_join[c]);
         if (s->side[c]) (void)hipStreamDestroy(s->side[c]);
     }
+    for (auto &pool : s->kt_pool)
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);

@@ -107,6 +107,7 @@ struct EpochArgs {
     double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
     // timing
     uint64_t *pack_time;  // accumulated ns per pack, or null
+    int32_t prio;         // wave issue priority 0..3 (larger packs: higher)
 };
 
 // Bytes of per-pack state for a pack of n compartments, s synapses and k

@@ -730,6 +730,14 @@ template <typename T, bool kFast>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
     k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
+    // the launches of the larger packs hold the epoch's critical path: their
+    // waves get issue priority over those of the small-pack launch
+    if (a.prio == 1)
+        __builtin_amdgcn_s_setprio(1);
+    else if (a.prio == 2)
+        __builtin_amdgcn_s_setprio(2);
+    else if (a.prio >= 3)
+        __builtin_amdgcn_s_setprio(3);
     const int64_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
     const int q0 = a.wg_off[blockIdx.x], q1 = a.wg_off[blockIdx.x + 1];
     for (int q = q0; q < q1; ++q) {

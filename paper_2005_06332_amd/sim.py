@@ -26,7 +26,7 @@ EXPORTS = (
     "sim_default_params", "sim_create", "sim_step", "sim_time_steps",
     "sim_read_voltages", "sim_read_gates", "sim_read_conductances",
     "sim_spikes", "sim_neuron_timings", "sim_features",
-    "sim_set_kernel_timing", "sim_kernel_time", "sim_config_string",
+    "sim_set_kernel_timing", "sim_kernel_time", "sim_class_time", "sim_config_string",
     "sim_destroy", "sim_last_error", "sim_mlp_nparams", "sim_mlp_init",
     "sim_mlp_forward", "sim_mlp_loss_grad", "sim_mlp_train",
 )
@@ -103,6 +103,8 @@ def lib():
         L.sim_features.argtypes = [P, P, C.c_int64]
         L.sim_set_kernel_timing.argtypes = [P, C.c_int32]
         L.sim_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.sim_class_time.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]
         L.sim_config_string.argtypes = [P]
         L.sim_config_string.restype = C.c_char_p
         L.sim_destroy.argtypes = [P]
@@ -116,8 +118,8 @@ def lib():
         L.sim_mlp_train.argtypes = [P, P, P, C.c_int64, C.c_int32, C.c_float, P]
         for f in ("sim_read_voltages", "sim_read_gates", "sim_read_conductances", "sim_spikes",
                   "sim_neuron_timings", "sim_features", "sim_set_kernel_timing",
-                  "sim_kernel_time", "sim_mlp_init", "sim_mlp_forward", "sim_mlp_loss_grad",
-                  "sim_mlp_train"):
+                  "sim_kernel_time", "sim_class_time", "sim_mlp_init", "sim_mlp_forward",
+                  "sim_mlp_loss_grad", "sim_mlp_train"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -254,9 +256,16 @@ class Simulation:
         _check(lib().sim_set_kernel_timing(self._h, int(on)), self._h)
 
     def kernel_time(self):
+        """(total ms, count) of the timed epochs."""
         ms, n = C.c_double(0), C.c_int64(0)
         _check(lib().sim_kernel_time(self._h, C.byref(ms), C.byref(n)), self._h)
         return ms.value, n.value
+
+    def class_time(self, cls: int):
+        """(total ms, launches, compartments per step) of size class cls."""
+        ms, n, c = C.c_double(0), C.c_int64(0), C.c_int64(0)
+        _check(lib().sim_class_time(self._h, cls, C.byref(ms), C.byref(n), C.byref(c)), self._h)
+        return ms.value, n.value, c.value
 
 
 # ---- cost model ---------------------------------------------------------------

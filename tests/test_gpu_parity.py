@@ -1,9 +1,19 @@
 """GPU parity: the HIP library against the CPU oracle, element by element.
 
-Both sides receive the same seeded inputs. Floating-point tolerance: 1e-9 mV
-on every voltage (FP64 and FP32-gating modes alike, since both sides
-evaluate the same operations in the same order); spike trains must be
-identical. The tests also report how many voltages differ at all.
+Both sides receive the same seeded inputs; spike trains must be identical.
+
+Voltage tolerances:
+- exact solver (the elimination in the oracle's operation order): 1e-9 mV in
+  both precision modes; in practice the results are bitwise equal, and the
+  tests report how many voltages differ at all.
+- fast solver (division-free homogeneous elimination), FP64: 1e-9 mV. Its
+  per-step rounding differs from the oracle's by a few ulps of V (about
+  1e-14 mV), measured at 2.6e-11 mV after 200 steps of the full network.
+- fast solver, FP32 gating: 1e-4 mV. The gates see (float)V; a V that
+  differs by 1e-14 mV rounds to the other neighbouring float in about one
+  case in 1e8 compartment-steps, and each such case moves a gate by one
+  float ulp (6e-8 relative), which moves V by up to about 1e-5 mV over the
+  following steps (measured: 5.4e-6 mV after 200 steps of the full network).
 """
 import os
 import sys
@@ -16,6 +26,11 @@ from paper_2005_06332_amd import workload as W
 pytestmark = pytest.mark.gpu
 
 TOL_MV = 1e-9
+TOL_FAST_FP32_MV = 1e-4
+
+
+def tol(precision, solver):
+    return TOL_FAST_FP32_MV if (solver == 1 and precision == 1) else TOL_MV
 
 
 @pytest.fixture(scope="module")
@@ -30,13 +45,13 @@ def say(*a):
     sys.stdout.flush()
 
 
-def compare(tag, v_gpu, v_ref, s_gpu, s_ref):
+def compare(tag, v_gpu, v_ref, s_gpu, s_ref, tol_mv=TOL_MV):
     d = np.abs(v_gpu - v_ref)
     nz = int(np.count_nonzero(d))
     say(f"{tag}: max|dV|={d.max():.3e} mV, differing={nz}/{d.size}, "
         f"spikes gpu={len(s_gpu)} ref={len(s_ref)}")
     assert np.all(np.isfinite(v_gpu))
-    assert d.max() <= TOL_MV, tag
+    assert d.max() <= tol_mv, tag
     assert s_gpu.shape == s_ref.shape and np.array_equal(s_gpu, s_ref), tag
 
 
@@ -60,17 +75,21 @@ def run_pair(S, orc, prob, steps, precision, chunks=None, **kw):
     return out, (vr, sr, (mr, hr, nr), gr)
 
 
+@pytest.mark.parametrize("solver", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_config1_matches_oracle(S, orc, precision):
+def test_config1_matches_oracle(S, orc, precision, solver):
     prob = W.config1()
-    (v, s, gates, g), (vr, sr, gr_, gref) = run_pair(S, orc, prob, 400, precision)
-    compare(f"cfg1 prec={precision}", v, vr, s, sr)
+    (v, s, gates, g), (vr, sr, gr_, gref) = run_pair(S, orc, prob, 400, precision,
+                                                     solver=solver)
+    compare(f"cfg1 prec={precision} solver={solver}", v, vr, s, sr, tol(precision, solver))
+    gate_tol = 1e-12 if solver == 0 or precision == 0 else 1e-6
     for a, b in zip(gates, gr_):
-        assert np.max(np.abs(a - b)) <= 1e-12
+        assert np.max(np.abs(a - b)) <= gate_tol
     assert np.max(np.abs(g - gref)) <= 1e-12
     assert len(sr) > 0
 
 
+@pytest.mark.parametrize("solver", [0, 1])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("packing,sched,pack_comps,lds", [
     (0, 0, 0, 0),        # plain, one workgroup per pack
@@ -79,20 +98,23 @@ def test_config1_matches_oracle(S, orc, precision):
     (1, 1, 64, 0),       # one neuron per pack
     (1, 1, 600, 120),    # big packs in global scratch
 ])
-def test_multimorphology_matches_oracle(S, orc, precision, packing, sched, pack_comps, lds):
+def test_multimorphology_matches_oracle(S, orc, precision, solver, packing, sched, pack_comps,
+                                        lds):
     prob = W.mini(n_steps=240)
     (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 240, precision, packing=packing,
-                                            sched=sched, pack_comps=pack_comps, lds_comps=lds)
-    compare(f"mini prec={precision} pk={packing} sc={sched} pc={pack_comps} lds={lds}",
-            v, vr, s, sr)
+                                            sched=sched, pack_comps=pack_comps, lds_comps=lds,
+                                            solver=solver)
+    compare(f"mini prec={precision} solver={solver} pk={packing} sc={sched} pc={pack_comps} "
+            f"lds={lds}", v, vr, s, sr, tol(precision, solver))
     assert len(sr) > 0
 
 
-def test_partial_epochs_and_graph_replay_match(S, orc):
+@pytest.mark.parametrize("solver", [0, 1])
+def test_partial_epochs_and_graph_replay_match(S, orc, solver):
     prob = W.mini(seed=13, n_steps=300, delay_lo=40, delay_hi=90)
     chunks = [7, 33, 1, 79, 80, 100]
-    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 300, 1, chunks=chunks)
-    compare("mini partial epochs", v, vr, s, sr)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 300, 1, chunks=chunks, solver=solver)
+    compare(f"mini partial epochs solver={solver}", v, vr, s, sr, tol(1, solver))
 
 
 def test_variable_delays_match(S, orc):
@@ -136,14 +158,15 @@ def test_single_compartment_and_tiny_neurons(S, orc):
     compare("mini with n=1 neurons", v, vr, s, sr)
 
 
-def test_packing_and_launch_variants_are_bitwise_identical(S):
+@pytest.mark.parametrize("solver", [0, 1])
+def test_packing_and_launch_variants_are_bitwise_identical(S, solver):
     prob = W.mini(seed=29, n_steps=200, n_neurons=96)
     base = None
     for kw in (dict(packing=0), dict(packing=1, sched=1), dict(packing=1, sched=2),
                dict(packing=1, sched=1, threads=64), dict(packing=1, sched=1, threads=512),
                dict(packing=1, sched=1, pack_comps=2000), dict(packing=1, sched=1, lds_comps=64),
                dict(packing=1, use_graph=False), dict(packing=1, autotune=True)):
-        with S.Simulation(prob, **kw) as g:
+        with S.Simulation(prob, solver=solver, **kw) as g:
             g.step(200)
             out = (g.voltages(), g.spikes())
             say(kw, g.config)
@@ -165,23 +188,39 @@ def test_validation_errors_do_not_touch_the_device(S):
     with pytest.raises(S.SimError) as e:
         S.Simulation(prob, epoch_steps=41)
     assert e.value.code == S.SIM_EINVAL
+    with pytest.raises(S.SimError) as e:
+        S.Simulation(prob, solver=2)
+    assert e.value.code == S.SIM_EINVAL
 
 
 def test_full_size_multimorphology_matches_oracle(S, orc):
     """The 16384-neuron multi-morphology network (9.29e6 compartments, 1.6e6
     synapses) in the launch configuration bench.py times (count packing,
-    autotuned layout), 200 steps = 5 epochs, every voltage and every spike
-    against the oracle."""
+    autotuned layout, fast solver, FP32 gating), 200 steps = 5 epochs, every
+    voltage and every spike against the FP32-gating oracle (stated bound
+    1e-4 mV) and against the FP64 oracle (the error of FP32 gating itself,
+    stated bound 1e-2 mV; measured 2.8e-4 mV), then the exact solver against
+    the FP32-gating oracle at 1e-9 mV."""
     prob = W.make(3)
     steps = 200
     say(f"case full cfg3 N={prob['n_comp'].shape[0]} C={int(prob['comp_off'][-1])} steps={steps}")
-    with S.Simulation(prob, packing=S.PACK_COUNT, autotune=True) as g:
-        say("  config:", g.config)
-        g.step(steps)
-        v, s = g.voltages(), g.spikes()
+    outs = {}
+    for solver in (1, 0):
+        with S.Simulation(prob, packing=S.PACK_COUNT, autotune=(solver == 1),
+                          solver=solver) as g:
+            say("  config:", g.config)
+            g.step(steps)
+            outs[solver] = (g.voltages(), g.spikes())
     ref = orc.Sim(prob, max_steps=steps)
     ref.step(steps)
     vr, sr = ref.voltages(), ref.spikes()
     ref.close()
-    compare("full cfg3", v, vr, s, sr)
+    ref64 = orc.Sim(prob, max_steps=steps, precision=0)
+    ref64.step(steps)
+    vr64, sr64 = ref64.voltages(), ref64.spikes()
+    ref64.close()
+    v, s = outs[1]
+    compare("full cfg3 fast vs FP32-gating oracle", v, vr, s, sr, TOL_FAST_FP32_MV)
+    compare("full cfg3 fast vs FP64 oracle", v, vr64, s, sr64, 1e-2)
+    compare("full cfg3 exact vs FP32-gating oracle", outs[0][0], vr, outs[0][1], sr)
     assert len(sr) > 1000
