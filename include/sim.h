@@ -130,6 +130,9 @@ typedef struct {
                             compartments (the two larger classes get 2x and
                             4x, capped by the CU's LDS); packs beyond every
                             budget use global scratch. 0 = 1100 */
+    int32_t lds_classes; /* size classes in use, 1..3 (0 = 2); packs beyond
+                            the largest budget in use keep their state in
+                            global scratch inside that class's launch */
     int32_t use_graph;   /* 1: replay whole epochs from a captured hipGraph */
     int32_t record_timings; /* 1: per-pack wall-clock time in the kernel */
     const float *cost_model;   /* MLP parameters (sim_mlp_nparams floats) for

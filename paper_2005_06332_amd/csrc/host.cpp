@@ -170,6 +170,7 @@ struct Variant {
     int lds_limit = 64 * 1024;  // bytes of LDS per workgroup
     int sched = SIM_SCHED_PERSISTENT;
     int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
+    int nclass = 2;  // LDS size classes in use (1..kClasses)
 };
 
 template <typename X>
@@ -309,6 +310,8 @@ void validate(const sim_params_t *P, const sim_morphology_t *M, const sim_channe
     if (P->threads != 0 && (P->threads < 64 || P->threads > 1024 || P->threads % 64))
         throw fail(SIM_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
     if (P->pack_comps < 0 || P->lds_comps < 0) throw fail(SIM_EINVAL, "negative size");
+    if (P->lds_classes < 0 || P->lds_classes > 3)
+        throw fail(SIM_EINVAL, "lds_classes must be 0 (default) or 1..3");
     if (M->n_neurons < 1) throw fail(SIM_EINVAL, "n_neurons must be >= 1");
     if (!M->comp_offset || !M->parent || !M->length_um || !M->diam_um || !M->mech ||
         !M->detector || !M->i_ext_nA)
@@ -503,7 +506,9 @@ void build_layout(sim_t *s, Variant v) {
     s->syn_perm.reserve(s->S);
     int64_t scratch = 0;
     // size classes: LDS budgets lds_limit, 2x, 4x, ... capped at the CU's LDS;
-    // the last class also takes the packs that fit nowhere (global state)
+    // the last class in use also takes the packs that fit nowhere (their
+    // state in global scratch, their tables in LDS)
+    const int ncls = std::max(1, std::min(kClasses, v.nclass));
     int64_t cls_budget[kClasses], lds_cls[kClasses];
     for (int c = 0; c < kClasses; ++c) {
         cls_budget[c] = std::min<int64_t>((int64_t)v.lds_limit << c, s->max_lds);
@@ -681,7 +686,7 @@ void build_layout(sim_t *s, Variant v) {
         const int64_t bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
         if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
         int c = 0;
-        while (c + 1 < kClasses && d.tbytes + bytes > cls_budget[c]) ++c;
+        while (c + 1 < ncls && d.tbytes + bytes > cls_budget[c]) ++c;
         if (d.tbytes + bytes <= cls_budget[c]) {
             d.global_mem = 0;
             lds_cls[c] = std::max(lds_cls[c], d.tbytes + bytes);
@@ -1067,9 +1072,9 @@ std::string describe(const sim_t *s) {
     int nglob = 0;
     for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
     snprintf(buf, sizeof buf,
-             "threads=%d pack_comps=%d lds_limit=%d sched=%s packs=%zu global_packs=%d "
+             "threads=%d pack_comps=%d lds_limit=%d classes=%d sched=%s packs=%zu global_packs=%d "
              "wg=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s solver=%s packing=%s",
-             s->var.threads, s->var.pack_comps, s->var.lds_limit,
+             s->var.threads, s->var.pack_comps, s->var.lds_limit, s->var.nclass,
              (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
                                                                                     : "persistent",
              s->packs.size(), nglob, s->launch[0].n_wg, s->launch[1].n_wg, s->launch[2].n_wg,
@@ -1114,6 +1119,12 @@ void autotune(sim_t *s, Variant base) {
             v.sched = SIM_SCHED_DISPATCH;
             cand.push_back(v);
         }
+    for (int nc : {1, 3}) {  // the largest packs in fewer or more launches
+        Variant v = base;
+        v.sched = SIM_SCHED_DISPATCH;
+        v.nclass = nc;
+        cand.push_back(v);
+    }
     {
         Variant v = base;
         v.sched = SIM_SCHED_PERSISTENT;
@@ -1216,6 +1227,7 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
         v.threads = params->threads ? params->threads : 256;
         v.pack_comps = params->pack_comps ? params->pack_comps : 800;
         v.lds_limit = lds_for(s, params->lds_comps ? params->lds_comps : 1100);
+        if (params->lds_classes) v.nclass = params->lds_classes;
         v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
         if (params->autotune)
             autotune(s, v);

@@ -299,33 +299,50 @@ __device__ __forceinline__ void pivots_h(double *__restrict__ D, double *__restr
     R[i] = R[i] * y;
 }
 
-// Both sweeps walk a branch in blocks of kBlk compartments. The block's
+// Both sweeps walk a branch in blocks of kBlk compartments. A block's
 // coefficients are read from LDS together (constant offsets from one
 // address, one round trip per block), then the dependent chain runs in
-// registers and each compartment's result is stored under a per-lane mask.
-// A lane whose branch ends inside a block reads up to kBlk-1 doubles beyond
-// the branch (inside the pack's arrays, or the slack after them) and runs
-// its chain on those values without storing anything; the values it needs
-// afterwards are read back from LDS.
+// registers. The blocks are aligned so that all but one are full: the
+// backward sweep takes the partial block first (at the tip, with selects
+// that keep the state across its unused slots) and then full blocks that end
+// exactly at the base, so the base state is in registers when the chain
+// ends; the forward sweep takes full blocks from the base and the partial
+// block last (masked stores). A partial block reads up to kBlk-1 doubles
+// beyond the branch (inside the pack's arrays, or the slack after them) and
+// discards them.
 #ifndef MMH_SWEEP_BLOCK
 #define MMH_SWEEP_BLOCK 4
 #endif
 constexpr int kBlk = MMH_SWEEP_BLOCK;
 
-// The elimination along one branch, tip b1 down to base b0. kFast = false:
-// the operation order of the elimination, a correctly rounded division per
-// compartment (pivot d'_i, reduced right-hand side r'_i left in D and R).
-// kFast = true: the division-free homogeneous form. Along a branch the
-// pivots obey d'_{i-1} = D_{i-1} - e_i^2 / d'_i and the reduced right-hand
-// sides r'_{i-1} = R_{i-1} - e_i r'_i / d'_i; with d'_i = P_i / Q_i and
-// r'_i = S_i / Q_i (one common denominator) both become linear recurrences,
-//   P_{i-1} = D_{i-1} P_i - e_i^2 Q_i,  S_{i-1} = R_{i-1} P_i - e_i S_i,
-//   Q_{i-1} = P_i,
-// one fused multiply-add per compartment on each dependent chain. (P, Q, S)
-// is rescaled by a power of two (exact) after every block, and left in D, R
-// and Q (the V slot). The tip first subtracts the contributions of its child
-// branches (in descending base order); the base leaves e^2/d' and e r'/d'
-// for its parent.
+// One step of the elimination chain, compartment i+1 -> i (e = e_{i+1},
+// dn = D_i, rn = R_i). Exact: (P, S) = (d', r'), the operation order of the
+// elimination with a correctly rounded division. Fast: the division-free
+// homogeneous form, (P, q, S) with d' = P/q and r' = S/q:
+//   P_i = D_i P_{i+1} - e^2 q_{i+1},  S_i = R_i P_{i+1} - e S_{i+1},
+//   q_i = P_{i+1}.
+template <bool kFast>
+__device__ __forceinline__ void chain_step(const double e, const double dn, const double rn,
+                                           double &P, double &q, double &S) {
+    if constexpr (kFast) {
+        const double Pn = __builtin_fma(dn, P, -(e * e) * q);
+        const double Sn = __builtin_fma(-e, S, rn * P);
+        q = P;
+        P = Pn;
+        S = Sn;
+    } else {
+        const double f = div_nr(e, P);
+        P = dn - f * e;
+        S = rn - f * S;
+    }
+}
+
+// The elimination along one branch, tip b1 down to base b0 (the pivots and
+// reduced right-hand sides of Algorithm 1 restricted to the branch; the fast
+// form is rescaled by a power of two, exactly, after every block and leaves
+// (P, S, q) in D, R and Q). The tip first subtracts the contributions of its
+// child branches, in descending base order; the base leaves e^2/d' and
+// e r'/d' for its parent in entry cslot.
 template <bool kFast>
 __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *__restrict__ R,
                                                double *__restrict__ Q,
@@ -340,35 +357,51 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
     D[b.b1] = P;
     R[b.b1] = S;
     if constexpr (kFast) Q[b.b1] = q;
-    for (int i = b.b1; i > b.b0; i -= kBlk) {
+    const int L = b.b1 - b.b0;  // chain steps: compartments b1-1 .. b0
+    int i = b.b1;               // the next compartment is i-1
+    const int r = L % kBlk;
+    if (r != 0) {  // partial block at the tip
         const double *pe = Eo + i - (kBlk - 1);
         double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
         double e[kBlk], dn[kBlk], rn[kBlk];
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) {  // compartment i-1-j
+        for (int j = 0; j < kBlk; ++j) {
             e[j] = pe[kBlk - 1 - j];
             dn[j] = pd[kBlk - 1 - j];
             rn[j] = pr[kBlk - 1 - j];
         }
-        const int nv = i - b.b0;
 #pragma unroll
-        for (int j = 0; j < kBlk; ++j) {
-            if constexpr (kFast) {
-                const double Pn = __builtin_fma(dn[j], P, -(e[j] * e[j]) * q);
-                const double Sn = __builtin_fma(-e[j], S, rn[j] * P);
-                q = P;
-                P = Pn;
-                S = Sn;
-            } else {
-                const double f = div_nr(e[j], P);
-                P = dn[j] - f * e[j];
-                S = rn[j] - f * S;
-            }
-            if (j < nv) {
+        for (int j = 0; j < kBlk - 1; ++j) {
+            double P1 = P, q1 = q, S1 = S;
+            chain_step<kFast>(e[j], dn[j], rn[j], P1, q1, S1);
+            const bool ok = j < r;
+            P = ok ? P1 : P;
+            q = ok ? q1 : q;
+            S = ok ? S1 : S;
+            if (ok) {
                 pd[kBlk - 1 - j] = P;
                 pr[kBlk - 1 - j] = S;
                 if constexpr (kFast) pq[kBlk - 1 - j] = q;
             }
+        }
+        i -= r;
+    }
+    for (; i > b.b0; i -= kBlk) {  // full blocks down to the base
+        const double *pe = Eo + i - (kBlk - 1);
+        double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
+        double e[kBlk], dn[kBlk], rn[kBlk];
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            e[j] = pe[kBlk - 1 - j];
+            dn[j] = pd[kBlk - 1 - j];
+            rn[j] = pr[kBlk - 1 - j];
+        }
+#pragma unroll
+        for (int j = 0; j < kBlk; ++j) {
+            chain_step<kFast>(e[j], dn[j], rn[j], P, q, S);
+            pd[kBlk - 1 - j] = P;
+            pr[kBlk - 1 - j] = S;
+            if constexpr (kFast) pq[kBlk - 1 - j] = q;
         }
         if constexpr (kFast) {
             const int x = -__builtin_amdgcn_frexp_exp(P);
@@ -377,25 +410,34 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
             S = __builtin_amdgcn_ldexp(S, x);
         }
     }
-    if (b.par != kRootPar) {
+    if (b.par != kRootPar) {  // (P, S, q) is the base's state
         const double e0 = Eo[b.b0];
-        const double P0 = D[b.b0], S0 = R[b.b0];
         if constexpr (kFast) {
-            const double y = rcp_nr(P0);
-            CD[b.cslot] = ((e0 * e0) * Q[b.b0]) * y;
-            CR[b.cslot] = (e0 * S0) * y;
+            const double y = rcp_nr(P);
+            CD[b.cslot] = ((e0 * e0) * q) * y;
+            CR[b.cslot] = (e0 * S) * y;
         } else {
-            const double f = div_nr(e0, P0);
+            const double f = div_nr(e0, P);
             CD[b.cslot] = f * e0;
-            CR[b.cslot] = f * S0;
+            CR[b.cslot] = f * S;
         }
     }
 }
 
+// One back-substitution step: exact x = (r' - e x_parent)/d' correctly
+// rounded given y = RN(1/d'); fast x = h - g x_parent.
+template <bool kFast>
+__device__ __forceinline__ double subst_step(const double g, const double h, const double e,
+                                             const double y, const double x) {
+    if constexpr (kFast)
+        return __builtin_fma(-g, x, h);
+    else
+        return div_rn(h - e * x, g, y);
+}
+
 // Back-substitution along one branch, base to tip. Exact: V holds RN(1/d')
-// of the branch's own compartments on entry, x_i = (r'_i - e_i x_parent) /
-// d'_i correctly rounded. Fast: D and R hold g = e/d' and h = r'/d', x_i =
-// h_i - g_i x_parent. V[par] is already the parent's new voltage.
+// of the branch's own compartments on entry (D, R hold d', r'). Fast: D and R
+// hold g = e/d' and h = r'/d'. V[par] is already the parent's new voltage.
 template <bool kFast>
 __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const double *__restrict__ D,
                                               const double *__restrict__ R,
@@ -410,7 +452,8 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
         x = div_rn(t, D[b.b0], V[b.b0]);
     }
     V[b.b0] = x;
-    for (int i = b.b0 + 1; i <= b.b1; i += kBlk) {
+    int i = b.b0 + 1;
+    for (; i + kBlk - 1 <= b.b1; i += kBlk) {  // full blocks
         const double *pg = D + i, *ph = R + i, *pe = Eo + i;
         double *pv = V + i;
         double g[kBlk], h[kBlk], e[kBlk], y[kBlk];
@@ -423,13 +466,29 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
                 y[j] = pv[j];
             }
         }
-        const int nv = b.b1 - i + 1;
 #pragma unroll
         for (int j = 0; j < kBlk; ++j) {
-            if constexpr (kFast)
-                x = __builtin_fma(-g[j], x, h[j]);
-            else
-                x = div_rn(h[j] - e[j] * x, g[j], y[j]);
+            x = subst_step<kFast>(g[j], h[j], e[j], y[j], x);
+            pv[j] = x;
+        }
+    }
+    if (i <= b.b1) {  // partial block at the tip
+        const double *pg = D + i, *ph = R + i, *pe = Eo + i;
+        double *pv = V + i;
+        double g[kBlk], h[kBlk], e[kBlk], y[kBlk];
+#pragma unroll
+        for (int j = 0; j < kBlk - 1; ++j) {
+            g[j] = pg[j];
+            h[j] = ph[j];
+            if constexpr (!kFast) {
+                e[j] = pe[j];
+                y[j] = pv[j];
+            }
+        }
+        const int nv = b.b1 - i + 1;
+#pragma unroll
+        for (int j = 0; j < kBlk - 1; ++j) {
+            x = subst_step<kFast>(g[j], h[j], e[j], y[j], x);
             if (j < nv) pv[j] = x;
         }
     }
@@ -691,7 +750,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         MMH_PHASE(4);
 
         // ---- E: gates at V^{n+1}; detection --------------------------------
-#pragma unroll 2
+#pragma unroll 1
         for (int i = tid; i < n; i += NT) {
             if (topo_hh(topo[i])) {
                 T m = gm[i], h = gh[i], x = gn[i];

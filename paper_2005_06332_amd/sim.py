@@ -45,7 +45,8 @@ class Params(C.Structure):
         ("precision", C.c_int32), ("solver", C.c_int32), ("packing", C.c_int32),
         ("sched", C.c_int32),
         ("epoch_steps", C.c_int32), ("autotune", C.c_int32), ("threads", C.c_int32),
-        ("pack_comps", C.c_int32), ("lds_comps", C.c_int32), ("use_graph", C.c_int32),
+        ("pack_comps", C.c_int32), ("lds_comps", C.c_int32), ("lds_classes", C.c_int32),
+        ("use_graph", C.c_int32),
         ("record_timings", C.c_int32), ("cost_model", C.c_void_p), ("hip_stream", C.c_void_p),
     ]
 
@@ -148,7 +149,8 @@ class Simulation:
                  sched: int = SCHED_AUTO, autotune: bool = False, threads: int = 0,
                  pack_comps: int = 0, lds_comps: int = 0, use_graph: bool = True,
                  record_timings: bool = False, cost_model: np.ndarray | None = None,
-                 epoch_steps: int = 0, stream: int | None = None, solver: int | None = None):
+                 epoch_steps: int = 0, stream: int | None = None, solver: int | None = None,
+                 lds_classes: int = 0):
         L = lib()
         pr = prob["params"]
         ch = prob["channels"]
@@ -160,6 +162,7 @@ class Simulation:
             P.solver = int(solver)
         P.packing, P.sched, P.autotune = packing, sched, int(autotune)
         P.threads, P.pack_comps, P.lds_comps = threads, pack_comps, lds_comps
+        P.lds_classes = lds_classes
         P.use_graph, P.record_timings, P.epoch_steps = int(use_graph), int(record_timings), epoch_steps
         self._cm = None
         if cost_model is not None:
