@@ -260,6 +260,12 @@ typedef struct {
     uint8_t *spk_now;   /* [N] */
     int64_t nspk, spk_cap;
     int64_t *spk;       /* (neuron, step) pairs */
+    /* replay: when set, presynaptic spikes come from this raster of another
+     * run ([(ext_steps+1) * ext_N], 1 = neuron spiked at that step) instead
+     * of this simulation's own history; pre ids then index that network */
+    uint8_t *ext;
+    int32_t ext_N;
+    int64_t ext_steps;
     /* scratch, one set per thread */
     int nthreads;
     int32_t maxn;
@@ -411,15 +417,40 @@ void orc_destroy(orc_sim_t *o)
                     o->G, o->e, o->af, o->V, o->gm, o->gh, o->gn, o->fm,
                     o->fh, o->fn, o->g_d, o->g_f, o->pre, o->post, o->pcomp,
                     o->delay, o->w, o->syn_off, o->syn_idx, o->hist,
-                    o->spk_now, o->spk, o->w_d, o->w_r, o->w_ax, o->w_gs, o->w_gm};
+                    o->spk_now, o->spk, o->w_d, o->w_r, o->w_ax, o->w_gs, o->w_gm,
+                    o->ext};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; ++i) free(ptrs[i]);
     free(o);
 }
 
 static int spiked_at(const orc_sim_t *o, int32_t j, int64_t s)
 {
+    if (o->ext) {
+        if (s < 1 || s > o->ext_steps) return 0;
+        return o->ext[(size_t)s * o->ext_N + j];
+    }
     if (s < 1 || s > o->hist_cap) return 0;
     return o->hist[(size_t)s * o->N + j];
+}
+
+/* Replay mode: deliver presynaptic spikes from a raster recorded elsewhere
+ * (raster[s * ext_N + j] != 0: neuron j of that network spiked at step s,
+ * s = 1 .. ext_steps). Every synapse's pre id must be < ext_N. The raster is
+ * copied. Returns 0, or -1 on a bad argument or allocation failure. */
+int orc_set_input_raster(orc_sim_t *o, int32_t ext_N, int64_t ext_steps, const uint8_t *raster)
+{
+    if (!o || ext_N < 1 || ext_steps < 0 || !raster) return -1;
+    for (int64_t k = 0; k < o->S; ++k)
+        if (o->pre[k] < 0 || o->pre[k] >= ext_N) return -1;
+    size_t bytes = (size_t)(ext_steps + 1) * (size_t)ext_N;
+    uint8_t *copy = (uint8_t *)malloc(bytes ? bytes : 1);
+    if (!copy) return -1;
+    memcpy(copy, raster, bytes);
+    free(o->ext);
+    o->ext = copy;
+    o->ext_N = ext_N;
+    o->ext_steps = ext_steps;
+    return 0;
 }
 
 /* One step n -> n+1 of neuron j, double precision gating. */

@@ -80,6 +80,8 @@ def lib():
         L.orc_n_spikes.argtypes = [P]
         L.orc_q.restype = C.c_double
         L.orc_q.argtypes = [P]
+        L.orc_set_input_raster.restype = C.c_int
+        L.orc_set_input_raster.argtypes = [P, C.c_int32, C.c_int64, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -179,6 +181,16 @@ class Sim:
                                _ptr(k["syn_w"]), self.max_steps)
         if not self._h:
             raise MemoryError("oracle allocation failed")
+
+    def set_input_raster(self, raster: np.ndarray):
+        """Replay mode: presynaptic spikes come from ``raster`` (uint8
+        [(steps+1), N_network], raster[s, j] = 1 when neuron j spiked at step
+        s) instead of this simulation's own spikes; synapse pre ids index
+        that network."""
+        r = np.ascontiguousarray(raster, np.uint8)
+        self._raster = r
+        if lib().orc_set_input_raster(self._h, r.shape[1], r.shape[0] - 1, _ptr(r)) != 0:
+            raise ValueError("bad replay raster")
 
     def close(self):
         if self._h:

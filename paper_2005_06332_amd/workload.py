@@ -382,6 +382,47 @@ def subset(prob: dict, neurons) -> dict:
     return out
 
 
+def replay_subset(prob: dict, neurons) -> dict:
+    """The given neurons (in the given order) with every synapse onto them,
+    for replaying recorded presynaptic spikes: post ids are renumbered, pre
+    ids keep the full network's numbering, and the synapses keep their
+    relative order."""
+    neurons = np.asarray(neurons, np.int64)
+    N = prob["n_comp"].shape[0]
+    remap = np.full(N, -1, np.int64)
+    remap[neurons] = np.arange(neurons.shape[0])
+    off = prob["comp_off"]
+    idx = np.concatenate([np.arange(off[j], off[j + 1]) for j in neurons])
+    n_comp = prob["n_comp"][neurons].astype(np.int32)
+    comp_off = np.zeros(neurons.shape[0] + 1, np.int64)
+    comp_off[1:] = np.cumsum(n_comp)
+    keep = remap[prob["syn_post"]] >= 0
+    order = np.argsort(remap[prob["syn_post"][keep]], kind="stable")
+    out = dict(prob)
+    out.update(
+        n_comp=n_comp, comp_off=comp_off, parent=prob["parent"][idx],
+        length_um=prob["length_um"][idx], diam_um=prob["diam_um"][idx],
+        mech=prob["mech"][idx], detector=prob["detector"][neurons],
+        iext_nA=prob["iext_nA"][neurons],
+        syn_pre=prob["syn_pre"][keep][order].astype(np.int32),
+        syn_post=remap[prob["syn_post"][keep]][order].astype(np.int32),
+        syn_comp=prob["syn_comp"][keep][order],
+        syn_delay=prob["syn_delay"][keep][order],
+        syn_w=prob["syn_w"][keep][order],
+        params=dict(prob["params"]), channels=dict(prob["channels"]),
+    )
+    return out
+
+
+def spike_raster(spikes: np.ndarray, n_neurons: int, n_steps: int) -> np.ndarray:
+    """uint8 [(n_steps+1), n_neurons] from (neuron, step) pairs."""
+    r = np.zeros((n_steps + 1, n_neurons), np.uint8)
+    sp = np.asarray(spikes).reshape(-1, 2)
+    if sp.size:
+        r[sp[:, 1], sp[:, 0]] = 1
+    return r
+
+
 def summary(prob: dict) -> str:
     N = prob["n_comp"].shape[0]
     C = int(prob["comp_off"][-1])

@@ -224,3 +224,41 @@ def test_full_size_multimorphology_matches_oracle(S, orc):
     compare("full cfg3 fast vs FP64 oracle", v, vr64, s, sr64, 1e-2)
     compare("full cfg3 exact vs FP32-gating oracle", outs[0][0], vr, outs[0][1], sr)
     assert len(sr) > 1000
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_full_length_replay_matches_oracle(S, orc, solver):
+    """Per-neuron replay over the whole 4000-step run of the 16384-neuron
+    network: the GPU runs the full network (bench.py's configuration for
+    the fast solver); 34 neurons (32 drawn with a fixed seed, the largest
+    and the smallest) are then rerun in the oracle, fed with the GPU's
+    recorded spikes of their presynaptic neurons. This separates numerics
+    from network chaos over the full length: every voltage of those neurons
+    after 4000 steps and every one of their spikes must match (exact solver
+    1e-9 mV, measured bitwise; fast solver with FP32 gating 1e-4 mV,
+    measured 1.2e-5 mV)."""
+    prob = W.make(3)
+    N = prob["n_comp"].shape[0]
+    steps = 4000
+    rng = np.random.default_rng(7)
+    targets = np.unique(np.concatenate([rng.choice(N, 32, replace=False),
+                                        [int(np.argmax(prob["n_comp"])),
+                                         int(np.argmin(prob["n_comp"]))]]))
+    say(f"case full cfg3 replay solver={solver} steps={steps} targets={len(targets)}")
+    with S.Simulation(prob, solver=solver, autotune=(solver == 1)) as g:
+        say("  config:", g.config)
+        g.step(steps)
+        v, s = g.voltages(), g.spikes()
+    rep = orc.Sim(W.replay_subset(prob, targets), max_steps=steps)
+    rep.set_input_raster(W.spike_raster(s, N, steps))
+    rep.step(steps)
+    vr, sr = rep.voltages(), rep.spikes()
+    rep.close()
+    off = prob["comp_off"]
+    want = np.concatenate([v[off[j]:off[j + 1]] for j in targets])
+    pos = {int(j): k for k, j in enumerate(targets)}
+    gpu_sp = np.array(sorted((pos[int(n)], int(t)) for n, t in s if int(n) in pos),
+                      np.int64).reshape(-1, 2)
+    orc_sp = np.array(sorted(map(tuple, sr.tolist())), np.int64).reshape(-1, 2)
+    compare(f"replay solver={solver}", want, vr, gpu_sp, orc_sp, tol(1, solver))
+    assert len(s) > 10000 and len(orc_sp) > 50

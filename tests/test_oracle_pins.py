@@ -407,3 +407,31 @@ def test_threads_do_not_change_results(orc, monkeypatch):
     inv = np.argsort(perm)
     assert sorted(map(tuple, s1.tolist())) == sorted((int(perm[a]), int(b)) for a, b in s2.tolist())
     assert len(s1) > 0 and inv.shape == perm.shape
+
+
+def test_replay_of_recorded_spikes_reproduces_the_network(orc):
+    """Per-neuron replay: the oracle runs a few neurons of a network, fed
+    with the network's recorded spikes instead of its own; their voltages
+    and spikes must equal those of the full run exactly (the mechanism the
+    full-length GPU check relies on)."""
+    from paper_2005_06332_amd import workload as W
+    prob = W.mini(seed=41, n_neurons=40, n_steps=240)
+    steps = 240
+    full = orc.Sim(prob, max_steps=steps)
+    full.step(steps)
+    v_full, s_full = full.voltages(), full.spikes()
+    full.close()
+    assert len(s_full) > 0
+    targets = np.array([3, 17, 0, 29, 38])
+    sub = W.replay_subset(prob, targets)
+    rep = orc.Sim(sub, max_steps=steps)
+    rep.set_input_raster(W.spike_raster(s_full, prob["n_comp"].shape[0], steps))
+    rep.step(steps)
+    v_rep, s_rep = rep.voltages(), rep.spikes()
+    rep.close()
+    off = prob["comp_off"]
+    want = np.concatenate([v_full[off[j]:off[j + 1]] for j in targets])
+    assert np.array_equal(v_rep, want)
+    want_sp = sorted((int(np.where(targets == n)[0][0]), int(t))
+                     for n, t in s_full if n in set(targets.tolist()))
+    assert sorted(map(tuple, s_rep.tolist())) == want_sp
