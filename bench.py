@@ -61,10 +61,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def make_workload(name: str, neurons: int | None):
+def make_workload(name: str, neurons: int | None, precision: str | None = None):
     kw = {}
     if neurons:
         kw["n_neurons"] = neurons
+    if precision:
+        kw["precision"] = 0 if precision == "fp64" else 1
     cfg = int(name.replace("cfg", ""))
     prob = W.make(cfg, **kw)
     return prob
@@ -142,6 +144,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--neurons", type=int, default=0)
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="override the workload's precision (fp32 = FP32 gating, FP64 Hines)")
     ap.add_argument("--packing", default="count", choices=["plain", "count", "learned"])
     ap.add_argument("--solver", default="fast", choices=["exact", "fast"],
                     help="exact: the elimination in the reference operation order (bitwise "
@@ -163,7 +167,7 @@ def main():
     import torch
     from paper_2005_06332_amd import sim as S, costmodel
 
-    prob = make_workload(args.workload, args.neurons or None)
+    prob = make_workload(args.workload, args.neurons or None, args.precision)
     C = int(prob["comp_off"][-1])
     N = int(prob["n_comp"].shape[0])
     prec = int(prob["params"]["precision"])

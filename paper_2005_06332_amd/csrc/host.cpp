@@ -160,6 +160,7 @@ constexpr int kClasses = 3;
 // offset / list arrays.
 struct Launch {
     int n_wg = 0;
+    int threads = 256;
     size_t lds = 256;
     int32_t off0 = 0, list0 = 0;
 };
@@ -171,6 +172,7 @@ struct Variant {
     int sched = SIM_SCHED_PERSISTENT;
     int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
     int nclass = 2;  // LDS size classes in use (1..kClasses)
+    int cls_thr = 1;  // class c launches threads << (c * cls_thr) (at most the launch bound)
 };
 
 template <typename X>
@@ -712,6 +714,8 @@ void build_layout(sim_t *s, Variant v) {
     for (int c = 0; c < kClasses; ++c) {
         Launch &L = s->launch[c];
         L.lds = (size_t)std::max<int64_t>(lds_cls[c], 256);
+        L.threads = std::min(v.threads << (c * v.cls_thr),
+                             s->tsize == 8 ? kMaxThreadsF64 : kMaxThreadsF32);
         L.off0 = (int32_t)s->wg_off.size();
         L.list0 = (int32_t)s->wg_list.size();
         std::vector<int32_t> mine;  // in pack order (cost order for sorted packings)
@@ -994,7 +998,7 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         }
         EpochArgs ac = args(L);
         ac.prio = std::min(3, c * s->var.prio);
-        HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, s->var.threads, L.lds, s->side[c]));
+        HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, s->side[c]));
         if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
@@ -1005,7 +1009,7 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
             ev = kt_pair(s, 1);
             HIPCHK(hipEventRecord(ev.first, s->stream));
         }
-        HIPCHK(launch_epoch(args(S0), pr, s->solver, S0.n_wg, s->var.threads, S0.lds, s->stream));
+        HIPCHK(launch_epoch(args(S0), pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
         if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
     }
     for (int c = 1; c < kClasses; ++c)
@@ -1068,16 +1072,18 @@ void run_steps(sim_t *s, int64_t n) {
 }
 
 std::string describe(const sim_t *s) {
-    char buf[512];
+    char buf[640];
     int nglob = 0;
     for (auto &d : s->packs) nglob += d.global_mem ? 1 : 0;
     snprintf(buf, sizeof buf,
              "threads=%d pack_comps=%d lds_limit=%d classes=%d sched=%s packs=%zu global_packs=%d "
-             "wg=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s solver=%s packing=%s",
+             "wg=%d+%d+%d wg_threads=%d+%d+%d lds_bytes=%zu+%zu+%zu E=%d precision=%s solver=%s "
+             "packing=%s",
              s->var.threads, s->var.pack_comps, s->var.lds_limit, s->var.nclass,
              (s->P.packing == SIM_PACK_PLAIN || s->var.sched == SIM_SCHED_DISPATCH) ? "dispatch"
                                                                                     : "persistent",
              s->packs.size(), nglob, s->launch[0].n_wg, s->launch[1].n_wg, s->launch[2].n_wg,
+             s->launch[0].threads, s->launch[1].threads, s->launch[2].threads,
              s->launch[0].lds, s->launch[1].lds, s->launch[2].lds, s->E,
              s->precision == SIM_FP64 ? "fp64" : "fp32-gating",
              s->solver == SIM_SOLVE_FAST ? "fast" : "exact",
