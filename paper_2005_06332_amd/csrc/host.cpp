@@ -497,7 +497,7 @@ void build_layout(sim_t *s, Variant v) {
     std::vector<Branch> brs;
     std::vector<FwBranch> fws;
     // per-pack branch scratch (pack-local branch index = br_base + local)
-    std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0, cslot;
+    std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0;
     topo.reserve(s->C);
     lparent.reserve(s->C);
     len.reserve(s->C);
@@ -633,19 +633,15 @@ void build_layout(sim_t *s, Variant v) {
         }
         pos.assign(nbr, 0);
         for (int32_t k = 0; k < nbr; ++k) pos[order[k]] = k;
-        // child entries in record order; each child's slot among its siblings
+        // child entries (base compartments) in record order
         child0.assign(nbr, 0);
-        cslot.assign(nbr, 0xFFFF);
         {
             int32_t acc = 0;
             for (int32_t k = 0; k < nbr; ++k) {
                 const int32_t bb = order[k];
                 child0[k] = acc;
-                for (int32_t r = 0; r < nchild(bb); ++r) {
-                    const int32_t c = tch[tch_off[bb] + r];
-                    chl.push_back((uint16_t)tb0[c]);
-                    cslot[c] = acc + r;
-                }
+                for (int32_t r = 0; r < nchild(bb); ++r)
+                    chl.push_back((uint16_t)tb0[tch[tch_off[bb] + r]]);
                 acc += nchild(bb);
             }
         }
@@ -657,7 +653,8 @@ void build_layout(sim_t *s, Variant v) {
             r.child0 = (uint16_t)child0[k];
             r.nchild = (uint16_t)nchild(bb);
             r.par = (uint16_t)tpar[bb];
-            r.cslot = (uint16_t)cslot[bb];
+            for (int32_t c = 0; c < 2; ++c)
+                r.cb[c] = c < nchild(bb) ? (uint16_t)tb0[tch[tch_off[bb] + c]] : 0;
             brs.push_back(r);
         }
         // branch ids in the compartment words: positions in record order

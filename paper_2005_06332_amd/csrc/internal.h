@@ -33,14 +33,14 @@ __host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh
 // is the only child of the previous. Branch records of a pack are stored in
 // backward-sweep order (by height, longest chains first within a level), and
 // a branch's id is its position there. Its children (branches whose base
-// hangs off b1) occupy child entries child0 .. child0+nchild-1 in ascending
-// order of their bases: the child list holds their base compartments, and
-// the child contributions of the elimination live at the same entries (a
-// child leaves its own at entry cslot). par is the parent compartment of b0,
-// or kRootPar when b0 is the root of its neuron (then cslot is unused).
+// hangs off b1) occupy child-list entries child0 .. child0+nchild-1 in
+// ascending order of their bases; the entries hold the children's base
+// compartments, and cb[0], cb[1] repeat the first two. par is the parent
+// compartment of b0, or kRootPar when b0 is the root of its neuron.
 constexpr uint16_t kRootPar = 0xFFFF;
 struct alignas(16) Branch {
-    uint16_t b0, b1, child0, nchild, par, cslot, pad0, pad1;
+    uint16_t b0, b1, child0, nchild, par, pad;
+    uint16_t cb[2];
 };
 // Forward-sweep record (by depth, longest chains first within a level).
 struct alignas(8) FwBranch {
@@ -121,14 +121,13 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
     return b;
 }
 // Bytes of the pack's tables staged in LDS next to the state: backward and
-// forward branch records, child contributions (2 doubles per child entry),
-// synapse weights (T), level offsets, child list, synapse targets and run
-// lengths. Must match the carve-up in the kernel.
+// forward branch records, synapse weights (T), level offsets, child list,
+// synapse targets and run lengths. Must match the carve-up in the kernel.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn) {
     int64_t b = (int64_t)sizeof(Branch) * nbr + (int64_t)sizeof(FwBranch) * nbr;
-    b += 16 * nch + (int64_t)sizeof(T) * nsyn;
+    b += (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
     b += 2 * nch + 2 * 2 * nsyn;
     return (b + 15) / 16 * 16;

@@ -340,18 +340,44 @@ __device__ __forceinline__ void chain_step(const double e, const double dn, cons
 // The elimination along one branch, tip b1 down to base b0 (the pivots and
 // reduced right-hand sides of Algorithm 1 restricted to the branch; the fast
 // form is rescaled by a power of two, exactly, after every block and leaves
-// (P, S, q) in D, R and Q). The tip first subtracts the contributions of its
-// child branches, in descending base order; the base leaves e^2/d' and
-// e r'/d' for its parent in entry cslot.
+// (P, S, q) in D, R and Q). The base's state stays in D, R (and Q), where the
+// parent branch's tip reads it at the next level.
 template <bool kFast>
 __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *__restrict__ R,
                                                double *__restrict__ Q,
                                                const double *__restrict__ Eo, const Branch b,
-                                               double *__restrict__ CD, double *__restrict__ CR) {
+                                               const uint16_t *__restrict__ chl) {
+    // the tip takes the contributions e^2/d' and e r'/d' of its child
+    // branches, formed here from the base states the children left in D, R
+    // (and Q), and subtracted in descending base order
     double P = D[b.b1], S = R[b.b1];
-    for (int c = b.nchild - 1; c >= 0; --c) {
-        P = P - CD[b.child0 + c];
-        S = S - CR[b.child0 + c];
+    auto contribution = [&](const int j, double &cd, double &cr) {
+        const double e0 = Eo[j];
+        if constexpr (kFast) {
+            const double y = rcp_nr(D[j]);
+            cd = ((e0 * e0) * Q[j]) * y;
+            cr = (e0 * R[j]) * y;
+        } else {
+            const double f = div_nr(e0, D[j]);
+            cd = f * e0;
+            cr = f * R[j];
+        }
+    };
+    if (b.nchild == 2) {
+        double cd1, cr1, cd0, cr0;
+        contribution(b.cb[1], cd1, cr1);
+        contribution(b.cb[0], cd0, cr0);
+        P = P - cd1;
+        S = S - cr1;
+        P = P - cd0;
+        S = S - cr0;
+    } else {
+        for (int c = b.nchild - 1; c >= 0; --c) {
+            double cd, cr;
+            contribution(chl[b.child0 + c], cd, cr);
+            P = P - cd;
+            S = S - cr;
+        }
     }
     double q = 1.0;
     D[b.b1] = P;
@@ -408,18 +434,6 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
             P = __builtin_amdgcn_ldexp(P, x);
             q = __builtin_amdgcn_ldexp(q, x);
             S = __builtin_amdgcn_ldexp(S, x);
-        }
-    }
-    if (b.par != kRootPar) {  // (P, S, q) is the base's state
-        const double e0 = Eo[b.b0];
-        if constexpr (kFast) {
-            const double y = rcp_nr(P);
-            CD[b.cslot] = ((e0 * e0) * q) * y;
-            CR[b.cslot] = (e0 * S) * y;
-        } else {
-            const double f = div_nr(e0, P);
-            CD[b.cslot] = f * e0;
-            CR[b.cslot] = f * S;
         }
     }
 }
@@ -566,14 +580,12 @@ __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x,
 }
 
 // The pack's tables, staged in LDS for the whole epoch: backward and forward
-// branch records, child contributions (CD, CR), synapse weights, level
-// offsets, child list, synapse targets and run lengths. The layout must
-// match pack_table_bytes().
+// branch records, synapse weights, level offsets, child list, synapse targets
+// and run lengths. The layout must match pack_table_bytes().
 template <typename T>
 struct Tables {
     Branch *br;
     FwBranch *fw;
-    double *CD, *CR;
     T *sw;
     int32_t *lvl;
     uint16_t *chl, *scomp, *sseg;
@@ -584,9 +596,7 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
     Tables<T> t;
     t.br = (Branch *)smem;
     t.fw = (FwBranch *)(t.br + pk.nbr);
-    t.CD = (double *)(t.fw + pk.nbr);
-    t.CR = t.CD + pk.nch;
-    t.sw = (T *)(t.CR + pk.nch);
+    t.sw = (T *)(t.fw + pk.nbr);
     char *p = (char *)(t.sw + pk.nsyn);
     p = smem + (((p - smem) + 3) / 4) * 4;
     t.lvl = (int32_t *)p;
@@ -711,9 +721,9 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             for (int h = 0; h < pk.nbw; ++h) {
                 const int hi2 = lvl[min(h + 2, pk.nbw)];
                 const Branch nxt = br[min(hi + slot, pk.nbr - 1)];
-                if (lo + slot < hi) sweep_back_blk<kFast>(D, R, V, Eo, cur, tb.CD, tb.CR);
+                if (lo + slot < hi) sweep_back_blk<kFast>(D, R, V, Eo, cur, chl);
                 for (int q2 = lo + slot + NT; q2 < hi; q2 += NT)
-                    sweep_back_blk<kFast>(D, R, V, Eo, br[q2], tb.CD, tb.CR);
+                    sweep_back_blk<kFast>(D, R, V, Eo, br[q2], chl);
                 __syncthreads();
                 cur = nxt;
                 lo = hi;
