@@ -278,13 +278,6 @@ struct sim {
 
 namespace {
 
-void set_error(sim_t *s, const Error &e) {
-    if (s)
-        s->err = e.msg;
-    else
-        g_create_error = e.msg;
-}
-
 // ---------------------------------------------------------------------------
 // Validation: everything is checked before any device allocation.
 // ---------------------------------------------------------------------------

@@ -615,7 +615,7 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
 // the level has branches.
 template <typename T, bool kFast>
 __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
-                                         char *base, int64_t epoch, int pid) {
+                                         char *base, int64_t epoch) {
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
     const int slot = tid;
@@ -819,10 +819,9 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         // LDS instructions rather than generic (flat) ones
         if (pk.global_mem)
             run_pack<T, kFast>(a, pk, smem,
-                               a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch,
-                               pid);
+                               a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch);
         else
-            run_pack<T, kFast>(a, pk, smem, smem + pk.tbytes, epoch, pid);
+            run_pack<T, kFast>(a, pk, smem, smem + pk.tbytes, epoch);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
