@@ -60,10 +60,12 @@ constexpr float kLn2HiF = 0x1.62e4p-1f;
 constexpr float kLn2LoF = 0x1.7f7d1cp-20f;
 constexpr float kInvLn2F = 0x1.715476p+0f;
 
+// The argument is clamped to [-708, 709] ([-87, 88] in float), where the
+// result is a normal number; for every finite argument this is the same
+// function as clamping with comparisons (only a NaN argument differs, which a
+// valid state never produces).
 __device__ __forceinline__ double dexp(double x) {
-    if (x != x) return x;
-    if (x > 709.0) x = 709.0;
-    if (x < -708.0) x = -708.0;
+    x = __builtin_fmin(__builtin_fmax(x, -708.0), 709.0);
     const double k = __builtin_rint(x * kInvLn2D);
     double r = __builtin_fma(-k, kLn2HiD, x);
     r = __builtin_fma(-k, kLn2LoD, r);
@@ -86,9 +88,7 @@ __device__ __forceinline__ double dexp(double x) {
 }
 
 __device__ __forceinline__ float fexp(float x) {
-    if (x != x) return x;
-    if (x > 88.0f) x = 88.0f;
-    if (x < -87.0f) x = -87.0f;
+    x = __builtin_amdgcn_fmed3f(x, -87.0f, 88.0f);
     const float k = __builtin_rintf(x * kInvLn2F);
     float r = __builtin_fmaf(-k, kLn2HiF, x);
     r = __builtin_fmaf(-k, kLn2LoF, r);
@@ -133,6 +133,19 @@ __device__ __forceinline__ float fexprelr(float u) {
     return u / (fexp(u) - 1.0f);
 }
 
+// x / c for the rate constants c. Float: q = RN(x RN(1/c)), then Markstein's
+// correction with the exact residual x - q c, carrying the sign of q (which
+// only matters for x = -0). For c = 10, 18, 20 and 80 this equals the
+// correctly rounded quotient for every float with 1e-30 <= |x| <= 1e30 and
+// for x = +-0 (checked exhaustively); the rate arguments v + const are 0 or
+// at least ulp(40) in magnitude. Double: the IEEE quotient.
+__device__ __forceinline__ float div_const(float x, float c, float rc) {
+    const float q = x * rc;
+    const float r = __builtin_fmaf(-q, c, x);
+    return __builtin_copysignf(__builtin_fmaf(r, rc, q), q);
+}
+__device__ __forceinline__ double div_const(double x, double c, double) { return x / c; }
+
 template <typename T> struct Fn;
 template <> struct Fn<double> {
     static __device__ __forceinline__ double ex(double x) { return dexp(x); }
@@ -146,12 +159,12 @@ template <> struct Fn<float> {
 // Hodgkin-Huxley rates (1/ms) at v (mV), modern sign convention.
 template <typename T>
 __device__ __forceinline__ void hh_rates(T v, T &am, T &bm, T &ah, T &bh, T &an, T &bn) {
-    am = Fn<T>::exr(-(v + T(40)) / T(10));
-    bm = T(4) * Fn<T>::ex(-(v + T(65)) / T(18));
-    ah = T(0.07) * Fn<T>::ex(-(v + T(65)) / T(20));
-    bh = T(1) / (Fn<T>::ex(-(v + T(35)) / T(10)) + T(1));
-    an = T(0.1) * Fn<T>::exr(-(v + T(55)) / T(10));
-    bn = T(0.125) * Fn<T>::ex(-(v + T(65)) / T(80));
+    am = Fn<T>::exr(div_const(-(v + T(40)), T(10), T(1) / T(10)));
+    bm = T(4) * Fn<T>::ex(div_const(-(v + T(65)), T(18), T(1) / T(18)));
+    ah = T(0.07) * Fn<T>::ex(div_const(-(v + T(65)), T(20), T(1) / T(20)));
+    bh = T(1) / (Fn<T>::ex(div_const(-(v + T(35)), T(10), T(1) / T(10))) + T(1));
+    an = T(0.1) * Fn<T>::exr(div_const(-(v + T(55)), T(10), T(1) / T(10)));
+    bn = T(0.125) * Fn<T>::ex(div_const(-(v + T(65)), T(80), T(1) / T(80)));
 }
 
 // Exponential Euler: x <- x_inf + (x - x_inf) exp(-dt (a + b)).
