@@ -315,14 +315,13 @@ __device__ __forceinline__ void pivots_h(double *__restrict__ D, double *__restr
 // Both sweeps walk a branch in blocks of kBlk compartments. A block's
 // coefficients are read from LDS together (constant offsets from one
 // address, one round trip per block), then the dependent chain runs in
-// registers. The blocks are aligned so that all but one are full: the
-// backward sweep takes the partial block first (at the tip, with selects
-// that keep the state across its unused slots) and then full blocks that end
-// exactly at the base, so the base state is in registers when the chain
-// ends; the forward sweep takes full blocks from the base and the partial
-// block last (masked stores). A partial block reads up to kBlk-1 doubles
-// beyond the branch (inside the pack's arrays, or the slack after them) and
-// discards them.
+// registers. Every block but the last is full and stores unmasked; the last,
+// partial block (at the base for the backward sweep, at the tip for the
+// forward sweep) masks its stores and lets the chain run on past the branch
+// in registers, which nothing reads afterwards (a parent branch takes its
+// children's base states from LDS). A partial block reads up to kBlk-1
+// doubles beyond the branch (inside the pack's arrays, or the slack after
+// them) and discards them.
 #ifndef MMH_SWEEP_BLOCK
 #define MMH_SWEEP_BLOCK 4
 #endif
@@ -352,9 +351,9 @@ __device__ __forceinline__ void chain_step(const double e, const double dn, cons
 
 // The elimination along one branch, tip b1 down to base b0 (the pivots and
 // reduced right-hand sides of Algorithm 1 restricted to the branch; the fast
-// form is rescaled by a power of two, exactly, after every block and leaves
-// (P, S, q) in D, R and Q). The base's state stays in D, R (and Q), where the
-// parent branch's tip reads it at the next level.
+// form is rescaled by a power of two, exactly, after every full block and
+// leaves (P, S, q) in D, R and Q). The base's state stays in D, R (and Q),
+// where the parent branch's tip reads it at the next level.
 template <bool kFast>
 __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *__restrict__ R,
                                                double *__restrict__ Q,
@@ -396,36 +395,8 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
     D[b.b1] = P;
     R[b.b1] = S;
     if constexpr (kFast) Q[b.b1] = q;
-    const int L = b.b1 - b.b0;  // chain steps: compartments b1-1 .. b0
-    int i = b.b1;               // the next compartment is i-1
-    const int r = L % kBlk;
-    if (r != 0) {  // partial block at the tip
-        const double *pe = Eo + i - (kBlk - 1);
-        double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
-        double e[kBlk], dn[kBlk], rn[kBlk];
-#pragma unroll
-        for (int j = 0; j < kBlk; ++j) {
-            e[j] = pe[kBlk - 1 - j];
-            dn[j] = pd[kBlk - 1 - j];
-            rn[j] = pr[kBlk - 1 - j];
-        }
-#pragma unroll
-        for (int j = 0; j < kBlk - 1; ++j) {
-            double P1 = P, q1 = q, S1 = S;
-            chain_step<kFast>(e[j], dn[j], rn[j], P1, q1, S1);
-            const bool ok = j < r;
-            P = ok ? P1 : P;
-            q = ok ? q1 : q;
-            S = ok ? S1 : S;
-            if (ok) {
-                pd[kBlk - 1 - j] = P;
-                pr[kBlk - 1 - j] = S;
-                if constexpr (kFast) pq[kBlk - 1 - j] = q;
-            }
-        }
-        i -= r;
-    }
-    for (; i > b.b0; i -= kBlk) {  // full blocks down to the base
+    int i = b.b1;  // the next compartment is i-1
+    for (; i - kBlk >= b.b0; i -= kBlk) {  // full blocks from the tip
         const double *pe = Eo + i - (kBlk - 1);
         double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
         double e[kBlk], dn[kBlk], rn[kBlk];
@@ -447,6 +418,27 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
             P = __builtin_amdgcn_ldexp(P, x);
             q = __builtin_amdgcn_ldexp(q, x);
             S = __builtin_amdgcn_ldexp(S, x);
+        }
+    }
+    if (i > b.b0) {  // partial block at the base: stores masked, state not needed
+        const double *pe = Eo + i - (kBlk - 1);
+        double *pd = D + i - kBlk, *pr = R + i - kBlk, *pq = Q + i - kBlk;
+        double e[kBlk], dn[kBlk], rn[kBlk];
+#pragma unroll
+        for (int j = 0; j < kBlk - 1; ++j) {
+            e[j] = pe[kBlk - 1 - j];
+            dn[j] = pd[kBlk - 1 - j];
+            rn[j] = pr[kBlk - 1 - j];
+        }
+        const int nv = i - b.b0;
+#pragma unroll
+        for (int j = 0; j < kBlk - 1; ++j) {
+            chain_step<kFast>(e[j], dn[j], rn[j], P, q, S);
+            if (j < nv) {
+                pd[kBlk - 1 - j] = P;
+                pr[kBlk - 1 - j] = S;
+                if constexpr (kFast) pq[kBlk - 1 - j] = q;
+            }
         }
     }
 }
