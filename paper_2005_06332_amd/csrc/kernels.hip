@@ -461,17 +461,10 @@ template <bool kFast>
 __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const double *__restrict__ D,
                                               const double *__restrict__ R,
                                               const double *__restrict__ Eo, const FwBranch b) {
-    double x;
-    if constexpr (kFast) {
-        x = R[b.b0];
-        if (b.par != kRootPar) x = __builtin_fma(-D[b.b0], V[b.par], x);
-    } else {
-        double t = R[b.b0];
-        if (b.par != kRootPar) t = t - Eo[b.b0] * V[b.par];
-        x = div_rn(t, D[b.b0], V[b.b0]);
-    }
-    V[b.b0] = x;
-    int i = b.b0 + 1;
+    // the base is the first element of the first block, against the parent's
+    // new voltage (a root has none: its coupling e is +0, so 0 stands in)
+    double x = b.par != kRootPar ? V[b.par] : 0.0;
+    int i = b.b0;
     for (; i + kBlk - 1 <= b.b1; i += kBlk) {  // full blocks
         const double *pg = D + i, *ph = R + i, *pe = Eo + i;
         double *pv = V + i;
