@@ -279,25 +279,34 @@ def mini(seed: int = 11, n_neurons: int = 48, precision: int = 1,
 
 def size_group(seed: int = 7, n_neurons: int = 10000, mono: bool = False,
                precision: int = 1, n_steps: int = 400) -> dict:
-    """The paper's Section-4 test: sizes from a group of 20 random sizes whose
-    spread (max - min) is 700 and whose mean is 300, assigned to 10000
-    neurons; or every neuron at the mean size (mono-morphology)."""
+    """The paper's Section-4 imbalance test: a group of 20 neurons with random
+    sizes whose spread (max - min) is 700 compartments and whose mean is 300
+    (shifted up if needed so that every size is at least 12); each of the
+    n_neurons neurons is a copy of a member drawn uniformly from the group.
+    mono: every neuron is a copy of one neuron of the mean size (300). The
+    trees follow the cfg3 recipe with at most 32 branches."""
     rng = np.random.default_rng(seed)
     g = rng.random(20)
     g = (g - g.min()) / (g.max() - g.min()) * 700.0
     g = g - g.mean() + 300.0
     lo_shift = max(0.0, 12.0 - g.min())
     g = np.rint(g + lo_shift).astype(np.int64)
-    sizes = np.full(n_neurons, 300) if mono else g[rng.integers(0, 20, n_neurons)]
-    morphs = []
-    for j in range(n_neurons):
-        n = int(sizes[j])
+
+    def one(n):
         B = max(2, int(min(32, 2 * ((n - 1) // 4))))
         bpar, ch = _random_branch_tree(B, rng.random((B - 2) // 2))
         extra = n - 1 - 2 * B
         lens = 2 + rng.multinomial(extra, np.full(B, 1.0 / B))
         d0, d1 = _taper(rng, B)
-        morphs.append(_build_neuron(bpar, ch, lens, d0, d1))
+        return _build_neuron(bpar, ch, lens, d0, d1)
+
+    if mono:
+        proto = one(300)
+        morphs = [proto] * n_neurons
+    else:
+        group = [one(int(n)) for n in g]
+        pick = rng.integers(0, 20, n_neurons)
+        morphs = [group[k] for k in pick]
     return _assemble("size_group_mono" if mono else "size_group", seed, morphs,
                      _hh_all, rng, 100, lambda s: np.full(s, 40), 2.0,
                      n_steps, precision)
