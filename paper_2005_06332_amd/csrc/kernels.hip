@@ -361,37 +361,55 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
                                                const uint16_t *__restrict__ chl) {
     // the tip takes the contributions e^2/d' and e r'/d' of its child
     // branches, formed here from the base states the children left in D, R
-    // (and Q), and subtracted in descending base order
-    double P = D[b.b1], S = R[b.b1];
-    auto contribution = [&](const int j, double &cd, double &cr) {
-        const double e0 = Eo[j];
-        if constexpr (kFast) {
-            const double y = rcp_nr(D[j]);
-            cd = ((e0 * e0) * Q[j]) * y;
-            cr = (e0 * R[j]) * y;
+    // (and Q). Exact: subtracted in descending base order. Fast: merged in
+    // homogeneous form, d'/q - e^2 q_c/P_c over the common denominator
+    // q P_c (likewise r'), so the tip needs no division either; the merged
+    // state is rescaled by a power of two like the chain's.
+    double P = D[b.b1], S = R[b.b1], q = 1.0;
+    if constexpr (kFast) {
+        auto merge = [&](const int j) {
+            const double e0 = Eo[j], Pc = D[j], qc = Q[j], Sc = R[j];
+            const double Pn = __builtin_fma(P, Pc, -((e0 * e0) * qc) * q);
+            const double Sn = __builtin_fma(S, Pc, -(e0 * Sc) * q);
+            q = q * Pc;
+            P = Pn;
+            S = Sn;
+        };
+        if (b.nchild == 2) {
+            merge(b.cb[1]);
+            merge(b.cb[0]);
         } else {
-            const double f = div_nr(e0, D[j]);
-            cd = f * e0;
-            cr = f * R[j];
+            for (int c = b.nchild - 1; c >= 0; --c) merge(chl[b.child0 + c]);
         }
-    };
-    if (b.nchild == 2) {
-        double cd1, cr1, cd0, cr0;
-        contribution(b.cb[1], cd1, cr1);
-        contribution(b.cb[0], cd0, cr0);
-        P = P - cd1;
-        S = S - cr1;
-        P = P - cd0;
-        S = S - cr0;
+        if (b.nchild > 0) {
+            const int x = -__builtin_amdgcn_frexp_exp(P);
+            P = __builtin_amdgcn_ldexp(P, x);
+            q = __builtin_amdgcn_ldexp(q, x);
+            S = __builtin_amdgcn_ldexp(S, x);
+        }
     } else {
-        for (int c = b.nchild - 1; c >= 0; --c) {
-            double cd, cr;
-            contribution(chl[b.child0 + c], cd, cr);
-            P = P - cd;
-            S = S - cr;
+        auto contribution = [&](const int j, double &cd, double &cr) {
+            const double f = div_nr(Eo[j], D[j]);
+            cd = f * Eo[j];
+            cr = f * R[j];
+        };
+        if (b.nchild == 2) {
+            double cd1, cr1, cd0, cr0;
+            contribution(b.cb[1], cd1, cr1);
+            contribution(b.cb[0], cd0, cr0);
+            P = P - cd1;
+            S = S - cr1;
+            P = P - cd0;
+            S = S - cr0;
+        } else {
+            for (int c = b.nchild - 1; c >= 0; --c) {
+                double cd, cr;
+                contribution(chl[b.child0 + c], cd, cr);
+                P = P - cd;
+                S = S - cr;
+            }
         }
     }
-    double q = 1.0;
     D[b.b1] = P;
     R[b.b1] = S;
     if constexpr (kFast) Q[b.b1] = q;
