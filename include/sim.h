@@ -58,9 +58,12 @@ extern "C" {
 
 #define SIM_PACK_PLAIN 0    /* neurons in input order, one workgroup per pack,
                                hardware dispatch order */
-#define SIM_PACK_COUNT 1    /* cost = compartment count; sort + LPT */
-#define SIM_PACK_LEARNED 2  /* cost = MLP prediction (falls back to COUNT
-                               when no model is given) */
+#define SIM_PACK_COUNT 1    /* cost = compartment count; neurons in cost
+                               order go best-fit into packs that fill the
+                               LDS budget of their size class; packs run in
+                               decreasing summed cost (dispatch or LPT) */
+#define SIM_PACK_LEARNED 2  /* the same with cost = MLP prediction (falls
+                               back to COUNT when no model is given) */
 
 #define SIM_SCHED_AUTO 0       /* chosen by the autotuner, else DISPATCH */
 #define SIM_SCHED_PERSISTENT 1 /* one resident workgroup per slot; static LPT
@@ -125,7 +128,10 @@ typedef struct {
                             create and keep the fastest */
     int32_t threads;     /* workgroup size 64..1024 (multiple of 64; at most 512
                             in SIM_FP64), 0 = 256 */
-    int32_t pack_comps;  /* target compartments per pack, 0 = 800 */
+    int32_t pack_comps;  /* plain packing: target compartments per pack,
+                            0 = 800. Count and learned packing: cap on a
+                            pack's compartments, 0 = none (packs are filled
+                            best-fit to their LDS budget) */
     int32_t lds_comps;   /* LDS budget of the smallest pack class, in
                             compartments (the two larger classes get 2x and
                             4x, capped by the CU's LDS); packs beyond every

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <queue>
 #include <string>
@@ -167,7 +168,8 @@ struct Launch {
 
 struct Variant {
     int threads = 256;
-    int pack_comps = 1024;
+    int pack_comps = 1024;  // plain packing: target compartments per pack
+    int comp_cap = 0;       // count / learned packing: cap on a pack's compartments, 0 = none
     int lds_limit = 64 * 1024;  // bytes of LDS per workgroup
     int sched = SIM_SCHED_PERSISTENT;
     int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
@@ -449,14 +451,21 @@ void build_layout(sim_t *s, Variant v) {
     if (s->P.packing != SIM_PACK_PLAIN)
         std::stable_sort(s->order.begin(), s->order.end(),
                          [&](int32_t a, int32_t b) { return s->cost[a] > s->cost[b]; });
-    // packs: consecutive neurons (in that order) up to pack_comps compartments
     struct P0 {
         int32_t first, count;
         int64_t ncomp, nsyn;
         int32_t nbr;
     };
     std::vector<P0> pk;
-    {
+    // size classes: LDS budgets lds_limit, 2x, 4x, ... capped at the CU's LDS;
+    // the last class in use also takes the packs that fit nowhere (their
+    // state in global scratch, their tables in LDS)
+    const int ncls = std::max(1, std::min(kClasses, v.nclass));
+    int64_t cls_budget[kClasses];
+    for (int c = 0; c < kClasses; ++c)
+        cls_budget[c] = std::min<int64_t>((int64_t)v.lds_limit << c, s->max_lds);
+    if (s->P.packing == SIM_PACK_PLAIN) {
+        // consecutive neurons in generation order, up to pack_comps compartments
         P0 cur{0, 0, 0, 0, 0};
         for (int32_t q = 0; q < N; ++q) {
             const int32_t j = s->order[q];
@@ -475,6 +484,96 @@ void build_layout(sim_t *s, Variant v) {
             cur.nbr += nb;
         }
         pk.push_back(cur);
+    } else {
+        // Best-fit decreasing: neurons in cost order, each into the open pack
+        // with the least LDS left that still holds it (tables and state,
+        // exactly as the kernel lays them out); a neuron that fits no open
+        // pack opens one in the smallest size class that holds it alone. A
+        // pack's workgroup allocates its class's budget whatever it holds,
+        // so filling packs to the budget raises the compartments resident
+        // per CU. Packs are then ordered by their summed cost (the dispatch
+        // order of the workgroups).
+        struct Bin {
+            std::vector<int32_t> members;
+            int64_t n = 0, ns = 0;
+            int32_t nbr = 0, nch = 0, maxh = 0, maxd = 0;
+            int cls = 0;
+            double cost = 0.0;
+        };
+        auto bytes_of = [&](int64_t n, int64_t ns, int32_t nbr, int32_t nch, int32_t maxh,
+                            int32_t maxd, int64_t k) -> int64_t {
+            const int64_t nlev = (int64_t)maxh + maxd + 4;
+            return s->tsize == 8
+                       ? pack_table_bytes<double>(nbr, nch, nlev, ns) + pack_state_bytes<double>(n, ns, k)
+                       : pack_table_bytes<float>(nbr, nch, nlev, ns) + pack_state_bytes<float>(n, ns, k);
+        };
+        std::vector<Bin> bins;
+        std::multimap<int64_t, int32_t> open;  // LDS bytes left -> bin
+        std::vector<std::multimap<int64_t, int32_t>::iterator> where;
+        const int64_t base_bytes = bytes_of(0, 0, 0, 0, 0, 0, 0);
+        for (int32_t q = 0; q < N; ++q) {
+            const int32_t j = s->order[q];
+            const NeuronTopo &t = s->topo[j];
+            const int64_t n = s->off[j + 1] - s->off[j], ns = s->nsyn_of[j];
+            const int32_t nb = (int32_t)t.b0.size();
+            const int64_t alone = bytes_of(n, ns, nb, nb - 1, t.max_height, t.max_depth, 1);
+            int32_t chosen = -1;
+            int tries = 0;
+            for (auto it = open.lower_bound(alone - base_bytes); it != open.end() && tries < 32;
+                 ++it, ++tries) {
+                const Bin &B = bins[it->second];
+                if (B.members.size() >= 1024 || B.n + n > 32766 || B.nbr + nb > 32766 ||
+                    (v.comp_cap > 0 && B.n + n > v.comp_cap))
+                    continue;
+                const int64_t with = bytes_of(B.n + n, B.ns + ns, B.nbr + nb, B.nch + nb - 1,
+                                              std::max(B.maxh, t.max_height),
+                                              std::max(B.maxd, t.max_depth),
+                                              (int64_t)B.members.size() + 1);
+                if (with <= cls_budget[B.cls]) {
+                    chosen = it->second;
+                    break;
+                }
+            }
+            if (chosen < 0) {
+                Bin B;
+                while (B.cls + 1 < ncls && alone > cls_budget[B.cls]) ++B.cls;
+                bins.push_back(B);
+                where.push_back(open.end());
+                chosen = (int32_t)bins.size() - 1;
+            } else {
+                open.erase(where[chosen]);
+                where[chosen] = open.end();
+            }
+            Bin &B = bins[chosen];
+            B.members.push_back(j);
+            B.n += n;
+            B.ns += ns;
+            B.nbr += nb;
+            B.nch += nb - 1;
+            B.maxh = std::max(B.maxh, t.max_height);
+            B.maxd = std::max(B.maxd, t.max_depth);
+            B.cost += s->cost[j];
+            const int64_t used = bytes_of(B.n, B.ns, B.nbr, B.nch, B.maxh, B.maxd,
+                                          (int64_t)B.members.size());
+            if (used <= cls_budget[B.cls])  // (a pack too large for LDS stays alone)
+                where[chosen] = open.emplace(cls_budget[B.cls] - used, chosen);
+        }
+        std::vector<int32_t> bo(bins.size());
+        std::iota(bo.begin(), bo.end(), 0);
+        std::stable_sort(bo.begin(), bo.end(),
+                         [&](int32_t a, int32_t b) { return bins[a].cost > bins[b].cost; });
+        int32_t q = 0;
+        for (int32_t b : bo) {
+            P0 cur{q, 0, 0, 0, 0};
+            for (int32_t j : bins[b].members) {
+                s->order[q++] = j;
+                cur.count++;
+                cur.ncomp += s->off[j + 1] - s->off[j];
+                cur.nsyn += s->nsyn_of[j];
+                cur.nbr += (int32_t)s->topo[j].b0.size();
+            }
+            pk.push_back(cur);
+        }
     }
     const int npk = (int)pk.size();
     s->packs.assign(npk, PackDesc{});
@@ -500,15 +599,8 @@ void build_layout(sim_t *s, Variant v) {
     s->syn_perm.clear();
     s->syn_perm.reserve(s->S);
     int64_t scratch = 0;
-    // size classes: LDS budgets lds_limit, 2x, 4x, ... capped at the CU's LDS;
-    // the last class in use also takes the packs that fit nowhere (their
-    // state in global scratch, their tables in LDS)
-    const int ncls = std::max(1, std::min(kClasses, v.nclass));
-    int64_t cls_budget[kClasses], lds_cls[kClasses];
-    for (int c = 0; c < kClasses; ++c) {
-        cls_budget[c] = std::min<int64_t>((int64_t)v.lds_limit << c, s->max_lds);
-        lds_cls[c] = 0;
-    }
+    int64_t lds_cls[kClasses];
+    for (int c = 0; c < kClasses; ++c) lds_cls[c] = 0;
     std::vector<int> pclass(npk, 0);
     std::vector<std::pair<int64_t, int64_t>> segs;  // (local comp, synapse id)
 
@@ -1222,6 +1314,7 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
         Variant v;
         v.threads = params->threads ? params->threads : 256;
         v.pack_comps = params->pack_comps ? params->pack_comps : 800;
+        v.comp_cap = params->pack_comps;
         v.lds_limit = lds_for(s, params->lds_comps ? params->lds_comps : 1100);
         if (params->lds_classes) v.nclass = params->lds_classes;
         v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
