@@ -91,8 +91,9 @@ def time_run(S, prob, steps, warmup, packing, cost_model=None, autotune=True, st
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    # launch timing on: every epoch is launched directly and each size-class
-    # launch is bracketed by HIP events on the stream it runs on
+    # launch timing on: whole epochs replay from the captured graphs, with HIP
+    # events around each replay on the simulator's stream, and each
+    # size-class launch timing its own span on the device
     g.set_kernel_timing(True)
     with torch.cuda.stream(stream):
         ev0.record(stream)
@@ -184,8 +185,8 @@ def main():
                      autotune=not args.no_autotune, stream=stream, solver=solver)
     config_str = g.config
     E = int(config_str.split("E=")[1].split()[0])
-    # the dominant kernel: the launch of size class 0 (most packs), timed
-    # with HIP events on its own stream over the timed region
+    # the dominant kernel: the launch of size class 0 (most packs), its
+    # duration over the timed region from its own device-side span
     cls = [g.class_time(c) for c in range(3)]
     epoch_ms, epochs = g.kernel_time()
     g.close()

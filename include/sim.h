@@ -193,18 +193,22 @@ int sim_neuron_timings(sim_t *sim, double *out_ns, int64_t cap, int32_t reset);
  * [n_neurons][16], float) that the cost model consumes. */
 int sim_features(sim_t *sim, float *out, int64_t cap);
 
-/* Launch timing, off by default. While on, sim_step launches every epoch
- * directly (no graph replay) and records HIP events around each epoch on the
- * simulator's stream and around each size-class launch on the stream that
- * launch runs on; sim_step reads them back before it returns. Turning it on
- * (again) resets the totals. */
+/* Launch timing, off by default. While on, sim_step records HIP events on
+ * the simulator's stream around each graph replay (or directly launched
+ * epoch), and sim_step reads them back before it returns. Each size-class
+ * launch also times itself on the device: the span from its first
+ * workgroup's start to its last workgroup's end, in the device's constant
+ * clock (the epoch kernel keeps these totals always; graph replays carry
+ * them, where events inside a graph are not updated by replays). Turning it
+ * on (again) waits for the stream and resets all totals. */
 int sim_set_kernel_timing(sim_t *sim, int32_t on);
 /* Total device time (ms) of the epochs (fork to join of the concurrent
  * size-class launches) and their count. */
 int sim_kernel_time(sim_t *sim, double *ms, int64_t *launches);
 /* For size class cls (0..2, 0 = the smallest LDS budget, normally holding
- * most packs): total device time (ms) of its launches, their count, and the
- * compartments the class advances per step. Any output may be NULL. */
+ * most packs): total device time (ms) of its launches (first workgroup start
+ * to last workgroup end), their count, and the compartments the class
+ * advances per step. Any output may be NULL. */
 int sim_class_time(sim_t *sim, int32_t cls, double *ms, int64_t *launches, int64_t *comps);
 
 /* Launch configuration actually used (after autotuning), as text. */

@@ -265,10 +265,14 @@ struct sim {
     bool kt_on = false;
     double kt_ms = 0;
     int64_t kt_launches = 0;
-    // launch timing: event pairs (epoch span, then one per size class) taken
-    // from pools, read back once per sim_step
-    std::vector<hipEvent_t> kt_pool[kClasses + 1];
-    int kt_used[kClasses + 1] = {};
+    // launch timing: HIP event pairs around each epoch (or graph replay of
+    // kt_ep[u] epochs) on the simulator's stream, taken from a pool and read
+    // back once per sim_step; each size-class launch times itself on the
+    // device (d_ktimer, 8 words per class, see EpochArgs::ktimer)
+    std::vector<hipEvent_t> kt_pool;
+    std::vector<int> kt_ep;
+    int kt_used = 0;
+    DBuf<uint64_t> d_ktimer;
     double kt_cls_ms[kClasses] = {};
     int64_t kt_cls_n[kClasses] = {};
     int64_t cls_comps[kClasses] = {};  // compartments of each size class
@@ -1016,34 +1020,43 @@ void assign_scratch(sim_t *s) {
     }
 }
 
-// Two events of pool k for one timed launch (created on first use).
-std::pair<hipEvent_t, hipEvent_t> kt_pair(sim_t *s, int k) {
-    auto &pool = s->kt_pool[k];
-    int &u = s->kt_used[k];
-    while ((int)pool.size() < u + 2) {
+// Two events of the pool for one timed span of `epochs` epochs (created on
+// first use).
+std::pair<hipEvent_t, hipEvent_t> kt_pair(sim_t *s, int epochs) {
+    while ((int)s->kt_pool.size() < s->kt_used + 2) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
-        pool.push_back(e);
+        s->kt_pool.push_back(e);
     }
-    u += 2;
-    return {pool[u - 2], pool[u - 1]};
+    s->kt_ep.resize(s->kt_pool.size() / 2);
+    s->kt_ep[s->kt_used / 2] = epochs;
+    s->kt_used += 2;
+    return {s->kt_pool[s->kt_used - 2], s->kt_pool[s->kt_used - 1]};
 }
 
-// Read back and reset the event pairs recorded since the last call.
+// Re-arm the device launch timers and clear their totals (stream idle).
+void ktimer_reset(sim_t *s) {
+    std::vector<uint64_t> init(8 * kClasses, 0);
+    for (int c = 0; c < kClasses; ++c) init[8 * c] = ~0ull;
+    HIPCHK(hipMemcpy(s->d_ktimer.p, init.data(), sizeof(uint64_t) * init.size(),
+                     hipMemcpyHostToDevice));
+}
+
+// Read back the epoch spans recorded since the last call (stream idle), and
+// the device timers' totals per size class.
 void kt_collect(sim_t *s) {
-    for (int k = 0; k <= kClasses; ++k) {
-        for (int u = 0; u + 1 < s->kt_used[k]; u += 2) {
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, s->kt_pool[k][u], s->kt_pool[k][u + 1]));
-            if (k == 0) {
-                s->kt_ms += ms;
-                s->kt_launches++;
-            } else {
-                s->kt_cls_ms[k - 1] += ms;
-                s->kt_cls_n[k - 1]++;
-            }
-        }
-        s->kt_used[k] = 0;
+    for (int u = 0; u + 1 < s->kt_used; u += 2) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, s->kt_pool[u], s->kt_pool[u + 1]));
+        s->kt_ms += ms;
+        s->kt_launches += s->kt_ep[u / 2];
+    }
+    s->kt_used = 0;
+    uint64_t t[8 * kClasses];
+    HIPCHK(hipMemcpy(t, s->d_ktimer.p, sizeof t, hipMemcpyDeviceToHost));
+    for (int c = 0; c < kClasses; ++c) {
+        s->kt_cls_ms[c] = (double)t[8 * c + 4] * s->tick_ns * 1e-6;
+        s->kt_cls_n[c] = (int64_t)t[8 * c + 5];
     }
 }
 
@@ -1052,8 +1065,9 @@ void kt_collect(sim_t *s) {
 // joined back into the main stream (also inside a captured graph).
 void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
     const int pr = s->precision == SIM_FP64 ? 0 : 1;
-    auto args = [&](const Launch &L) {
+    auto args = [&](const Launch &L, int c) {
         EpochArgs a = make_args(s);
+        a.ktimer = s->d_ktimer.p + 8 * c;
         a.wg_off = s->d_wg_off.p + L.off0;
         a.wg_list = s->d_wg_list.p + L.list0;
         a.epoch = epoch;
@@ -1073,27 +1087,14 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
             forked = true;
         }
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (s->kt_on) {
-            ev = kt_pair(s, c + 1);
-            HIPCHK(hipEventRecord(ev.first, s->side[c]));
-        }
-        EpochArgs ac = args(L);
+        EpochArgs ac = args(L, c);
         ac.prio = std::min(3, c * s->var.prio);
         HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, s->side[c]));
-        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
     const Launch &S0 = s->launch[0];
-    if (S0.n_wg > 0) {
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (s->kt_on) {
-            ev = kt_pair(s, 1);
-            HIPCHK(hipEventRecord(ev.first, s->stream));
-        }
-        HIPCHK(launch_epoch(args(S0), pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
-        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
-    }
+    if (S0.n_wg > 0)
+        HIPCHK(launch_epoch(args(S0, 0), pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
     for (int c = 1; c < kClasses; ++c)
         if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
 }
@@ -1121,17 +1122,26 @@ void run_steps(sim_t *s, int64_t n) {
         const int64_t ep = s->step / E;
         const int t0 = (int)(s->step % E);
         const int64_t full = (t0 == 0) ? n / E : 0;
-        if (full > 0 && s->P.use_graph && !s->kt_on) {
+        if (full > 0 && s->P.use_graph) {
             if (!s->exec1) capture(s, 1, s->graph1, s->exec1);
             if (!s->execK) capture(s, s->graphK_epochs, s->graphK, s->execK);
             HIPCHK(hipMemcpy(s->d_epoch.p, &ep, sizeof(int64_t), hipMemcpyHostToDevice));
+            auto replay = [&](hipGraphExec_t ex, int epochs) {
+                std::pair<hipEvent_t, hipEvent_t> ev{};
+                if (s->kt_on) {
+                    ev = kt_pair(s, epochs);
+                    HIPCHK(hipEventRecord(ev.first, s->stream));
+                }
+                HIPCHK(hipGraphLaunch(ex, s->stream));
+                if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
+            };
             int64_t left = full;
             while (left >= s->graphK_epochs) {
-                HIPCHK(hipGraphLaunch(s->execK, s->stream));
+                replay(s->execK, s->graphK_epochs);
                 left -= s->graphK_epochs;
             }
             while (left > 0) {
-                HIPCHK(hipGraphLaunch(s->exec1, s->stream));
+                replay(s->exec1, 1);
                 left -= 1;
             }
             s->step += full * E;
@@ -1141,7 +1151,7 @@ void run_steps(sim_t *s, int64_t n) {
         const int t1 = (int)std::min<int64_t>(E, t0 + n);
         std::pair<hipEvent_t, hipEvent_t> ev{};
         if (s->kt_on) {
-            ev = kt_pair(s, 0);
+            ev = kt_pair(s, 1);
             HIPCHK(hipEventRecord(ev.first, s->stream));
         }
         launch_range(s, ep, t0, t1, false);
@@ -1310,6 +1320,8 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
         HIPCHK(hipEventCreate(&s->ev0));
         HIPCHK(hipEventCreate(&s->ev1));
         s->d_epoch.alloc(1);
+        s->d_ktimer.alloc(8 * kClasses);
+        ktimer_reset(s);
         compute_cost(s);
         Variant v;
         v.threads = params->threads ? params->threads : 256;
@@ -1474,7 +1486,15 @@ int sim_features(sim_t *s, float *out, int64_t cap) {
 
 int sim_set_kernel_timing(sim_t *s, int32_t on) {
     if (!s) return SIM_EINVAL;
+    try {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        ktimer_reset(s);
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    }
     s->kt_on = on != 0;
+    s->kt_used = 0;
     s->kt_ms = 0;
     s->kt_launches = 0;
     for (int c = 0; c < kClasses; ++c) {
@@ -1511,14 +1531,13 @@ void sim_destroy(sim_t *s) {
     fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
     fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
     fr(s->d_sseg); fr(s->d_chl); fr(s->d_fw); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
-    fr(s->d_hist); fr(s->d_ptime);
+    fr(s->d_hist); fr(s->d_ptime); fr(s->d_ktimer);
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     for (int c = 1; c < kClasses; ++c) {
         if (s->ev_join[c]) (void)hipEventDestroy(s->ev_join[c]);
         if (s->side[c]) (void)hipStreamDestroy(s->side[c]);
     }
-    for (auto &pool : s->kt_pool)
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->kt_pool) (void)hipEventDestroy(e);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);

@@ -107,6 +107,10 @@ struct EpochArgs {
     double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
     // timing
     uint64_t *pack_time;  // accumulated ns per pack, or null
+    // launch timer of this size class (device clock ticks): [0] earliest
+    // workgroup start, [1] latest workgroup end, [2] finished workgroups of
+    // the running launch, [4] summed launch spans, [5] launches
+    uint64_t *ktimer;
     int32_t prio;         // wave issue priority 0..3 (larger packs: higher)
 };
 

@@ -824,6 +824,8 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
     else if (a.prio >= 3)
         __builtin_amdgcn_s_setprio(3);
     const int64_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
+    if (a.ktimer && threadIdx.x == 0)
+        atomicMin((unsigned long long *)&a.ktimer[0], (unsigned long long)wall_clock64());
     const int q0 = a.wg_off[blockIdx.x], q1 = a.wg_off[blockIdx.x + 1];
     for (int q = q0; q < q1; ++q) {
         const int pid = a.wg_list[q];
@@ -842,6 +844,25 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
                       (unsigned long long)(wall_clock64() - tstart));
+    }
+    // The launch's span, from the first workgroup's start to the last one's
+    // end: every workgroup raises the end mark before it counts itself
+    // done, so the last to count sees the final marks, adds the span to the
+    // class total and re-arms the timer for the next launch (which the
+    // stream orders after this one).
+    if (a.ktimer && threadIdx.x == 0) {
+        unsigned long long *kt = (unsigned long long *)a.ktimer;
+        atomicMax(&kt[1], (unsigned long long)wall_clock64());
+        __threadfence();
+        if (atomicAdd(&kt[2], 1ull) == (unsigned long long)gridDim.x - 1) {
+            __threadfence();
+            const unsigned long long t0 = atomicAdd(&kt[0], 0ull), t1 = atomicAdd(&kt[1], 0ull);
+            atomicAdd(&kt[4], t1 - t0);
+            atomicAdd(&kt[5], 1ull);
+            atomicExch(&kt[0], ~0ull);
+            atomicExch(&kt[1], 0ull);
+            atomicExch(&kt[2], 0ull);
+        }
     }
 }
 
