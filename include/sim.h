@@ -58,12 +58,14 @@ extern "C" {
 
 #define SIM_PACK_PLAIN 0    /* neurons in input order, one workgroup per pack,
                                hardware dispatch order */
-#define SIM_PACK_COUNT 1    /* cost = compartment count; neurons in cost
-                               order go best-fit into packs that fill the
-                               LDS budget of their size class; packs run in
-                               decreasing summed cost (dispatch or LPT) */
-#define SIM_PACK_LEARNED 2  /* the same with cost = MLP prediction (falls
-                               back to COUNT when no model is given) */
+#define SIM_PACK_COUNT 1    /* neurons by decreasing compartment count go
+                               best-fit into packs that fill the LDS budget
+                               of their size class; packs run in decreasing
+                               summed compartment count (dispatch or LPT) */
+#define SIM_PACK_LEARNED 2  /* the same packs, run in decreasing predicted
+                               time (the MLP's largest prediction among a
+                               pack's neurons); falls back to COUNT when no
+                               model is given */
 
 #define SIM_SCHED_AUTO 0       /* chosen by the autotuner, else DISPATCH */
 #define SIM_SCHED_PERSISTENT 1 /* one resident workgroup per slot; static LPT

@@ -452,9 +452,14 @@ void build_layout(sim_t *s, Variant v) {
     // neuron order
     s->order.resize(N);
     std::iota(s->order.begin(), s->order.end(), 0);
+    // count and learned packing fill their packs in decreasing compartment
+    // count (ties by cost); the cost then orders the packs
+    const bool learned = s->P.packing == SIM_PACK_LEARNED && !s->cost_model.empty();
     if (s->P.packing != SIM_PACK_PLAIN)
-        std::stable_sort(s->order.begin(), s->order.end(),
-                         [&](int32_t a, int32_t b) { return s->cost[a] > s->cost[b]; });
+        std::stable_sort(s->order.begin(), s->order.end(), [&](int32_t a, int32_t b) {
+            const int64_t na = s->off[a + 1] - s->off[a], nb = s->off[b + 1] - s->off[b];
+            return na != nb ? na > nb : s->cost[a] > s->cost[b];
+        });
     struct P0 {
         int32_t first, count;
         int64_t ncomp, nsyn;
@@ -489,14 +494,17 @@ void build_layout(sim_t *s, Variant v) {
         }
         pk.push_back(cur);
     } else {
-        // Best-fit decreasing: neurons in cost order, each into the open pack
-        // with the least LDS left that still holds it (tables and state,
-        // exactly as the kernel lays them out); a neuron that fits no open
-        // pack opens one in the smallest size class that holds it alone. A
-        // pack's workgroup allocates its class's budget whatever it holds,
-        // so filling packs to the budget raises the compartments resident
-        // per CU. Packs are then ordered by their summed cost (the dispatch
-        // order of the workgroups).
+        // Best-fit decreasing: neurons by decreasing size, each into the open
+        // pack with the least LDS left that still holds it (tables and
+        // state, exactly as the kernel lays them out); a neuron that fits no
+        // open pack opens one in the smallest size class that holds it
+        // alone. A pack's workgroup allocates its class's budget whatever it
+        // holds, so filling packs to the budget raises the compartments
+        // resident per CU. Packs are then ordered by decreasing cost (the
+        // dispatch order of the workgroups, and the LPT order of persistent
+        // ones): summed compartment counts, or, with the learned model, the
+        // largest predicted time among the pack's neurons (its neurons run
+        // side by side, so the slowest one bounds the pack's sweeps).
         struct Bin {
             std::vector<int32_t> members;
             int64_t n = 0, ns = 0;
@@ -556,7 +564,7 @@ void build_layout(sim_t *s, Variant v) {
             B.nch += nb - 1;
             B.maxh = std::max(B.maxh, t.max_height);
             B.maxd = std::max(B.maxd, t.max_depth);
-            B.cost += s->cost[j];
+            B.cost = learned ? std::max(B.cost, s->cost[j]) : B.cost + s->cost[j];
             const int64_t used = bytes_of(B.n, B.ns, B.nbr, B.nch, B.maxh, B.maxd,
                                           (int64_t)B.members.size());
             if (used <= cls_budget[B.cls])  // (a pack too large for LDS stays alone)
@@ -634,7 +642,8 @@ void build_layout(sim_t *s, Variant v) {
             const int32_t q = pk[p].first + k;
             const int32_t j = s->order[q];
             s->pack_of_neuron[j] = p;
-            s->pack_cost[p] += s->cost[j];
+            s->pack_cost[p] = learned ? std::max(s->pack_cost[p], s->cost[j])
+                                      : s->pack_cost[p] + s->cost[j];
             const NeuronTopo &t = s->topo[j];
             const int64_t b = s->off[j];
             const int32_t n = t.n;
