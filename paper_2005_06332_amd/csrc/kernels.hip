@@ -50,8 +50,8 @@ namespace {
 // Elementary functions. exp: Cody & Waite argument reduction x = k ln2 + r
 // with ln2 split into a high part with trailing zero bits (k*hi exact) and a
 // low part, then the Taylor polynomial of e^r (degree 13 in double, 7 in
-// float) by Horner with fused multiply-adds, then scaling by 2^k through the
-// exponent field.
+// float) by Horner with fused multiply-adds, then the scaling by 2^k
+// (ldexp; exact, since the clamp keeps the result a normal number).
 // ---------------------------------------------------------------------------
 constexpr double kLn2HiD = 0x1.62e42feep-1;
 constexpr double kLn2LoD = 0x1.a39ef35793c76p-33;
@@ -83,8 +83,7 @@ __device__ __forceinline__ double dexp(double x) {
     p = __builtin_fma(p, r, 0x1p-1);                 // 1/2!
     p = __builtin_fma(p, r, 1.0);                    // 1/1!
     p = __builtin_fma(p, r, 1.0);                    // 1/0!
-    const long long e = (long long)k + 1023;
-    return p * __longlong_as_double(e << 52);
+    return __builtin_amdgcn_ldexp(p, (int)k);
 }
 
 __device__ __forceinline__ float fexp(float x) {
@@ -100,8 +99,35 @@ __device__ __forceinline__ float fexp(float x) {
     p = __builtin_fmaf(p, r, 0x1p-1f);          // 1/2!
     p = __builtin_fmaf(p, r, 1.0f);             // 1/1!
     p = __builtin_fmaf(p, r, 1.0f);             // 1/0!
-    const int e = (int)k + 127;
-    return p * __int_as_float(e << 23);
+    return __builtin_amdgcn_ldexpf(p, (int)k);
+}
+
+// Correctly rounded a / b for operands and quotients far from the overflow
+// and underflow limits (the rate arguments and gate coefficients of the HH
+// model, and the reciprocal pivots): hardware reciprocal, Newton steps, and
+// Markstein's residual corrections. This is the sequence the compiler emits
+// for IEEE division with its range-scaling and special-case steps left out,
+// which are identities on such operands, so the quotient is bit for bit the
+// IEEE one.
+__device__ __forceinline__ float div_core(float a, float b) {
+    float y = __builtin_amdgcn_rcpf(b);
+    const float e = __builtin_fmaf(-b, y, 1.0f);
+    y = __builtin_fmaf(e, y, y);
+    float q = a * y;
+    float r = __builtin_fmaf(-b, q, a);
+    q = __builtin_fmaf(r, y, q);
+    r = __builtin_fmaf(-b, q, a);
+    return __builtin_fmaf(r, y, q);
+}
+__device__ __forceinline__ double div_core(double a, double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = a * y;
+    const double r = __builtin_fma(-b, q, a);
+    return __builtin_fma(r, y, q);
 }
 
 // u / (e^u - 1): Bernoulli series B_2k/(2k)! u^2k near 0, the quotient elsewhere.
@@ -118,7 +144,7 @@ __device__ __forceinline__ double dexprelr(double u) {
         c = __builtin_fma(c, w, 0x1.5555555555555p-4);
         return __builtin_fma(c, w, __builtin_fma(-0.5, u, 1.0));
     }
-    return u / (dexp(u) - 1.0);
+    return div_core(u, dexp(u) - 1.0);
 }
 
 __device__ __forceinline__ float fexprelr(float u) {
@@ -130,7 +156,7 @@ __device__ __forceinline__ float fexprelr(float u) {
         c = __builtin_fmaf(c, w, 0x1.555556p-4f);
         return __builtin_fmaf(c, w, __builtin_fmaf(-0.5f, u, 1.0f));
     }
-    return u / (fexp(u) - 1.0f);
+    return div_core(u, fexp(u) - 1.0f);
 }
 
 // x / c for the rate constants c. Float: q = RN(x RN(1/c)), then Markstein's
@@ -162,7 +188,7 @@ __device__ __forceinline__ void hh_rates(T v, T &am, T &bm, T &ah, T &bh, T &an,
     am = Fn<T>::exr(div_const(-(v + T(40)), T(10), T(1) / T(10)));
     bm = T(4) * Fn<T>::ex(div_const(-(v + T(65)), T(18), T(1) / T(18)));
     ah = T(0.07) * Fn<T>::ex(div_const(-(v + T(65)), T(20), T(1) / T(20)));
-    bh = T(1) / (Fn<T>::ex(div_const(-(v + T(35)), T(10), T(1) / T(10))) + T(1));
+    bh = div_core(T(1), Fn<T>::ex(div_const(-(v + T(35)), T(10), T(1) / T(10))) + T(1));
     an = T(0.1) * Fn<T>::exr(div_const(-(v + T(55)), T(10), T(1) / T(10)));
     bn = T(0.125) * Fn<T>::ex(div_const(-(v + T(65)), T(80), T(1) / T(80)));
 }
@@ -171,7 +197,7 @@ __device__ __forceinline__ void hh_rates(T v, T &am, T &bm, T &ah, T &bh, T &an,
 template <typename T>
 __device__ __forceinline__ T gate_step(T x, T a, T b, T dt) {
     const T s = a + b;
-    const T xinf = a / s;
+    const T xinf = div_core(a, s);
     const T ex = Fn<T>::ex(-dt * s);
     return xinf + (x - xinf) * ex;
 }
@@ -263,23 +289,6 @@ __device__ __forceinline__ uint64_t event_mask(const uint64_t *hist, int32_t N, 
     return m;
 }
 
-// Correctly rounded a / b without range scaling: hardware reciprocal, two
-// Newton steps and one exact-residual correction. This is the sequence the
-// compiler emits for IEEE division with its range-scaling and special-case
-// steps removed; those are identities unless |a|, |b| or the quotient come
-// near the overflow or underflow limits, which the coefficients of a
-// compartmental model (conductances in uS, voltages in mV) never do.
-__device__ __forceinline__ double div_nr(double a, double b) {
-    double y = __builtin_amdgcn_rcp(b);
-    double e = __builtin_fma(-b, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-b, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    const double q = a * y;
-    const double r = __builtin_fma(-b, q, a);
-    return __builtin_fma(r, y, q);
-}
-
 // Correctly rounded t / d given y = RN(1/d): q = RN(t y) is within one ulp of
 // t/d, the residual t - q d is exact in one fused multiply-add, and
 // RN(q + r y) is then the correctly rounded quotient (Markstein's theorem;
@@ -343,7 +352,7 @@ __device__ __forceinline__ void chain_step(const double e, const double dn, cons
         P = Pn;
         S = Sn;
     } else {
-        const double f = div_nr(e, P);
+        const double f = div_core(e, P);
         P = dn - f * e;
         S = rn - f * S;
     }
@@ -389,7 +398,7 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
         }
     } else {
         auto contribution = [&](const int j, double &cd, double &cr) {
-            const double f = div_nr(Eo[j], D[j]);
+            const double f = div_core(Eo[j], D[j]);
             cd = f * Eo[j];
             cr = f * R[j];
         };
@@ -750,7 +759,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             if constexpr (kFast)
                 pivots_h(D, R, V, Eo, i);
             else
-                V[i] = div_nr(1.0, D[i]);
+                V[i] = div_core(1.0, D[i]);
         }
         __syncthreads();
         MMH_PHASE(3);
