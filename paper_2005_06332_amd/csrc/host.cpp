@@ -251,7 +251,7 @@ struct sim {
     DBuf<uint32_t> d_topo;
     DBuf<uint16_t> d_scomp, d_sseg, d_chl;
     DBuf<Branch> d_br;
-    DBuf<FwBranch> d_fw;
+    DBuf<uint16_t> d_fw;
     DBuf<int64_t> d_ncomp0, d_epoch;
     DBuf<uint64_t> d_hist, d_ptime;
     int64_t hist_epochs = 0;
@@ -599,7 +599,7 @@ void build_layout(sim_t *s, Variant v) {
     std::vector<int32_t> spre, sdel;
     std::vector<uint16_t> scomp, sseg, chl;
     std::vector<Branch> brs;
-    std::vector<FwBranch> fws;
+    std::vector<uint16_t> fws;  // forward order: record ids
     // per-pack branch scratch (pack-local branch index = br_base + local)
     std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0;
     topo.reserve(s->C);
@@ -770,7 +770,7 @@ void build_layout(sim_t *s, Variant v) {
                 return chain_len(x, false) > chain_len(y, false);
             });
             for (int32_t bb : lev)
-                fws.push_back(FwBranch{(uint16_t)tb0[bb], (uint16_t)tb1[bb], (uint16_t)tpar[bb], 0});
+                fws.push_back((uint16_t)pos[bb]);
             lvl.push_back((int32_t)(fws.size() - d.br0));
         }
         d.nch = (int32_t)chl.size() - d.ch0;

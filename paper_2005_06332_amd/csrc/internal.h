@@ -42,17 +42,13 @@ struct alignas(16) Branch {
     uint16_t b0, b1, child0, nchild, par, pad;
     uint16_t cb[2];
 };
-// Forward-sweep record (by depth, longest chains first within a level).
-struct alignas(8) FwBranch {
-    uint16_t b0, b1, par, pad;
-};
 
 struct PackDesc {
     int64_t comp0;   // first compartment (packed index)
     int64_t syn0;    // first synapse (packed index)
     int32_t ncomp, nsyn;
     int32_t neur0, nneur;  // packed neuron range
-    int32_t br0, nbr;      // branch table range (backward and forward records)
+    int32_t br0, nbr;      // branch table range (records and forward order)
     int32_t ch0;           // child list / child contribution offset
     int32_t lv0;           // level offsets: nbw+1 backward then nfw+1 forward
     int32_t nbw, nfw;      // number of height / depth levels
@@ -86,7 +82,7 @@ struct EpochArgs {
     const void *niext;        // injected current (T)
     // per pack tables
     const Branch *br;
-    const FwBranch *fw;
+    const uint16_t *fw;  // forward-sweep order: record ids by depth, longest chains first
     const uint16_t *chl;
     const int32_t *lvl;
     // spike history: hist[epoch * n_neurons + input id] = bit t set when the
@@ -124,16 +120,16 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
     b += 64;  // slack: the blocked sweeps read up to 3 doubles past a branch
     return b;
 }
-// Bytes of the pack's tables staged in LDS next to the state: backward and
-// forward branch records, synapse weights (T), level offsets, child list,
-// synapse targets and run lengths. Must match the carve-up in the kernel.
+// Bytes of the pack's tables staged in LDS next to the state: branch records,
+// synapse weights (T), level offsets, the forward order, child list, synapse
+// targets and run lengths. Must match the carve-up in the kernel.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn) {
-    int64_t b = (int64_t)sizeof(Branch) * nbr + (int64_t)sizeof(FwBranch) * nbr;
+    int64_t b = (int64_t)sizeof(Branch) * nbr;
     b += (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
-    b += 2 * nch + 2 * 2 * nsyn;
+    b += 2 * nbr + 2 * nch + 2 * 2 * nsyn;
     return (b + 15) / 16 * 16;
 }
 

@@ -487,7 +487,7 @@ __device__ __forceinline__ double subst_step(const double g, const double h, con
 template <bool kFast>
 __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const double *__restrict__ D,
                                               const double *__restrict__ R,
-                                              const double *__restrict__ Eo, const FwBranch b) {
+                                              const double *__restrict__ Eo, const Branch b) {
     // the base is the first element of the first block, against the parent's
     // new voltage (a root has none: its coupling e is +0, so 0 stands in)
     double x = b.par != kRootPar ? V[b.par] : 0.0;
@@ -604,13 +604,14 @@ __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x,
     x = gate_step<T>(x, an, bn, dt);
 }
 
-// The pack's tables, staged in LDS for the whole epoch: backward and forward
-// branch records, synapse weights, level offsets, child list, synapse targets
-// and run lengths. The layout must match pack_table_bytes().
+// The pack's tables, staged in LDS for the whole epoch: branch records (in
+// backward order), synapse weights, level offsets, the forward order (record
+// ids), child list, synapse targets and run lengths. The layout must match
+// pack_table_bytes().
 template <typename T>
 struct Tables {
     Branch *br;
-    FwBranch *fw;
+    uint16_t *fw;
     T *sw;
     int32_t *lvl;
     uint16_t *chl, *scomp, *sseg;
@@ -620,12 +621,12 @@ template <typename T>
 __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk) {
     Tables<T> t;
     t.br = (Branch *)smem;
-    t.fw = (FwBranch *)(t.br + pk.nbr);
-    t.sw = (T *)(t.fw + pk.nbr);
+    t.sw = (T *)(t.br + pk.nbr);
     char *p = (char *)(t.sw + pk.nsyn);
     p = smem + (((p - smem) + 3) / 4) * 4;
     t.lvl = (int32_t *)p;
-    t.chl = (uint16_t *)(t.lvl + pk.nbw + pk.nfw + 2);
+    t.fw = (uint16_t *)(t.lvl + pk.nbw + pk.nfw + 2);
+    t.chl = t.fw + pk.nbr;
     t.scomp = t.chl + pk.nch;
     t.sseg = t.scomp + pk.nsyn;
     return t;
@@ -653,7 +654,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 #endif
     {
         const Branch *gbr = a.br + pk.br0;
-        const FwBranch *gfw = a.fw + pk.br0;
+        const uint16_t *gfw = a.fw + pk.br0;
         for (int k = tid; k < pk.nbr; k += NT) {
             tb.br[k] = gbr[k];
             tb.fw[k] = gfw[k];
@@ -767,15 +768,15 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         // ---- D: forward sweep by depth -------------------------------------
         {
             const int32_t *flv = lvl + pk.nbw + 1;
-            const FwBranch *fw = tb.fw;
+            const uint16_t *fw = tb.fw;
             int lo = flv[0], hi = flv[1];
-            FwBranch cur = fw[min(lo + slot, pk.nbr - 1)];
+            Branch cur = br[fw[min(lo + slot, pk.nbr - 1)]];
             for (int h = 0; h < pk.nfw; ++h) {
                 const int hi2 = flv[min(h + 2, pk.nfw)];
-                const FwBranch nxt = fw[min(hi + slot, pk.nbr - 1)];
+                const Branch nxt = br[fw[min(hi + slot, pk.nbr - 1)]];
                 if (lo + slot < hi) sweep_fwd_blk<kFast>(V, D, R, Eo, cur);
                 for (int q2 = lo + slot + NT; q2 < hi; q2 += NT)
-                    sweep_fwd_blk<kFast>(V, D, R, Eo, fw[q2]);
+                    sweep_fwd_blk<kFast>(V, D, R, Eo, br[fw[q2]]);
                 __syncthreads();
                 cur = nxt;
                 lo = hi;
