@@ -160,8 +160,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the simulator's multi-GPU sharding is a "
-              "design (one RCCL allgather of spike bits per epoch), not part of this build.",
+        print("bench.py runs on exactly one GPU: sharding the network over several GPUs "
+              "(one RCCL allgather of spike bits per epoch) is designed but not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
