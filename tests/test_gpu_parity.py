@@ -226,6 +226,21 @@ def test_full_size_multimorphology_matches_oracle(S, orc):
     assert len(sr) > 1000
 
 
+@pytest.mark.parametrize("cfg,precision,solver,steps", [
+    (2, 0, 0, 80), (2, 0, 1, 80), (4, 1, 1, 80), (4, 1, 0, 80),
+])
+def test_other_full_size_configs_match_oracle(S, orc, cfg, precision, solver, steps):
+    """The other full-size workloads against the oracle in the same precision,
+    in the layout bench.py times (autotuned, count packing): cfg2 (8192
+    identical neurons of 1000 compartments, all-FP64) and cfg4 (32768
+    multi-morphology neurons, FP32 gating), every voltage and every spike."""
+    prob = W.make(cfg)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, steps, precision, solver=solver,
+                                            autotune=True)
+    compare(f"full cfg{cfg} prec={precision} solver={solver}", v, vr, s, sr,
+            tol(precision, solver))
+
+
 @pytest.mark.parametrize("solver", [0, 1])
 def test_full_length_replay_matches_oracle(S, orc, solver):
     """Per-neuron replay over the whole 4000-step run of the 16384-neuron
