@@ -3,10 +3,11 @@
 // One workgroup advances one pack of neurons through the steps of an epoch
 // (E <= the smallest synaptic delay, so no spike produced inside the epoch
 // can reach a neuron before the epoch ends; Section 2 of the paper, two-level
-// time stepping). While it does so the pack's voltages, gates, conductances
-// and the per-step matrix (diagonal D and right-hand side R) stay in LDS (or,
-// for packs too large for LDS, in a private slice of global scratch that
-// stays resident in L2); only the time-invariant coefficients are re-read.
+// time stepping). While it does so the pack's voltages, off-diagonal,
+// synaptic conductances and the per-step matrix (diagonal D and right-hand
+// side R) stay in LDS (or, for packs too large for LDS, in a private slice
+// of global scratch); the gates and the time-invariant per-compartment
+// constants are read from global memory (mostly L2) every step.
 //
 // Per step and pack, in the order of the paper's update (Section 2):
 //   A  synaptic delivery from the spike history, per-compartment conductance
@@ -17,9 +18,11 @@
 //      by height so that every child is finished before its parent
 //   D  forward sweep of Algorithm 1, branches grouped by depth
 //   E  gates at V^{n+1} (exponential Euler); threshold-crossing detection
-// Every floating-point operation is performed in the order of Algorithm 1 as
-// written (children of a node eliminated in descending index order), with
-// no contraction, so the result does not depend on how neurons are packed.
+// The exact solver performs every floating-point operation in the order of
+// Algorithm 1 as written (children of a node eliminated in descending index
+// order), with no contraction; the fast solver reassociates the elimination
+// into a division-free homogeneous form. In both, a neuron's arithmetic does
+// not depend on how neurons are packed or launched.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
