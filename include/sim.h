@@ -198,18 +198,20 @@ int sim_features(sim_t *sim, float *out, int64_t cap);
 /* Launch timing, off by default. While on, sim_step records HIP events on
  * the simulator's stream around each graph replay (or directly launched
  * epoch), and sim_step reads them back before it returns. Each size-class
- * launch also times itself on the device: the span from its first
- * workgroup's start to its last workgroup's end, in the device's constant
- * clock (the epoch kernel keeps these totals always; graph replays carry
- * them, where events inside a graph are not updated by replays). Turning it
- * on (again) waits for the stream and resets all totals. */
+ * launch also times itself on the device: the span from a one-thread stamp
+ * kernel run just before it on its stream (so a wait for resources held by
+ * the concurrent launch counts) to its last workgroup's end, in the
+ * device's constant clock. The epoch kernel keeps these totals always, and
+ * graph replays carry them, where events inside a graph are not updated by
+ * replays. Turning it on (again) waits for the stream and resets all
+ * totals. */
 int sim_set_kernel_timing(sim_t *sim, int32_t on);
 /* Total device time (ms) of the epochs (fork to join of the concurrent
  * size-class launches) and their count. */
 int sim_kernel_time(sim_t *sim, double *ms, int64_t *launches);
 /* For size class cls (0..2, 0 = the smallest LDS budget, normally holding
- * most packs): total device time (ms) of its launches (first workgroup start
- * to last workgroup end), their count, and the compartments the class
+ * most packs): total device time (ms) of its launches (stamp before the
+ * launch to its last workgroup's end), their count, and the compartments the class
  * advances per step. Any output may be NULL. */
 int sim_class_time(sim_t *sim, int32_t cls, double *ms, int64_t *launches, int64_t *comps);
 

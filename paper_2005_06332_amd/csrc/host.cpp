@@ -1098,12 +1098,16 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
         EpochArgs ac = args(L, c);
         ac.prio = std::min(3, c * s->var.prio);
+        HIPCHK(launch_stamp(ac.ktimer, s->side[c]));
         HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
     const Launch &S0 = s->launch[0];
-    if (S0.n_wg > 0)
-        HIPCHK(launch_epoch(args(S0, 0), pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
+    if (S0.n_wg > 0) {
+        const EpochArgs a0 = args(S0, 0);
+        HIPCHK(launch_stamp(a0.ktimer, s->stream));
+        HIPCHK(launch_epoch(a0, pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
+    }
     for (int c = 1; c < kClasses; ++c)
         if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
 }

@@ -103,9 +103,10 @@ struct EpochArgs {
     double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
     // timing
     uint64_t *pack_time;  // accumulated ns per pack, or null
-    // launch timer of this size class (device clock ticks): [0] earliest
-    // workgroup start, [1] latest workgroup end, [2] finished workgroups of
-    // the running launch, [4] summed launch spans, [5] launches
+    // launch timer of this size class (device clock ticks): [0] start (set
+    // by k_stamp just before the launch, or the earliest workgroup start),
+    // [1] latest workgroup end, [2] finished workgroups of the running
+    // launch, [4] summed launch spans, [5] launches
     uint64_t *ktimer;
     int32_t prio;         // wave issue priority 0..3 (larger packs: higher)
 };
@@ -152,6 +153,7 @@ hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg,
                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_advance(int64_t *epoch, hipStream_t s);
+hipError_t launch_stamp(uint64_t *timer, hipStream_t s);
 hipError_t launch_decay_weights_convert(const double *w, void *out, int64_t n,
                                         int precision, hipStream_t s);
 hipError_t set_epoch_lds_limit(int bytes);

@@ -885,6 +885,14 @@ __global__ void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
         p[i] = v;
 }
 
+// Marks the start of a size-class launch in its timer: runs just before the
+// launch on the same stream, so the launch's span also covers any wait for
+// resources held by a concurrent launch (as a dispatch-level trace counts it).
+__global__ void k_stamp(uint64_t *timer) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        atomicMin((unsigned long long *)&timer[0], (unsigned long long)wall_clock64());
+}
+
 __global__ void k_advance(int64_t *epoch) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *epoch = *epoch + 1;
 }
@@ -954,6 +962,11 @@ hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
     int64_t nb = (n + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(uint64_t *timer, hipStream_t s) {
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, timer);
     return hipGetLastError();
 }
 
