@@ -335,7 +335,7 @@ __device__ __forceinline__ void pivots_h(double *__restrict__ D, double *__restr
 // doubles beyond the branch (inside the pack's arrays, or the slack after
 // them) and discards them.
 #ifndef MMH_SWEEP_BLOCK
-#define MMH_SWEEP_BLOCK 4
+#define MMH_SWEEP_BLOCK 5
 #endif
 constexpr int kBlk = MMH_SWEEP_BLOCK;
 
