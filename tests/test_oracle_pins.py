@@ -160,6 +160,76 @@ def test_isolated_hh_compartment_rests_near_minus_65(orc):
     assert len(s.spikes()) == 0
 
 
+def hh_space_clamped_spike_times(j_uA_cm2, t_end):
+    """Upward 0 mV crossings of the space-clamped HH membrane (Eq. 1 with no
+    axial term) under a constant current density, integrated by scipy's LSODA
+    at tight tolerance. Conductances in S/cm^2 times mV give mA/cm^2, hence
+    the factor 1e3 against uA/cm^2 and uF/cm^2."""
+    from scipy.integrate import solve_ivp
+    ch = W.CHANNELS
+
+    def rhs(t, y):
+        v, m, h, n = y
+        a = hh_rates_libm(v)
+        i_ion = (ch["gnabar"] * m ** 3 * h * (v - ch["ena"]) + ch["gkbar"] * n ** 4 * (v - ch["ek"])
+                 + ch["gl"] * (v - ch["el"]))
+        return [(j_uA_cm2 - 1e3 * i_ion) / ch["cm"],
+                a[0] * (1 - m) - a[1] * m, a[2] * (1 - h) - a[3] * h, a[4] * (1 - n) - a[5] * n]
+
+    def crossing(t, y):
+        return y[0]
+    crossing.direction = 1
+    a = hh_rates_libm(-65.0)
+    y0 = [-65.0, a[0] / (a[0] + a[1]), a[2] / (a[2] + a[3]), a[4] / (a[4] + a[5])]
+    sol = solve_ivp(rhs, (0.0, t_end), y0, method="LSODA", rtol=1e-10, atol=1e-12,
+                    events=crossing)
+    return sol.t_events[0]
+
+
+def test_driven_hh_compartment_converges_to_the_hh_ode(orc):
+    """A single HH compartment driven by 10 uA/cm^2 fires repetitively (about
+    68 Hz, the classic HH result). The oracle's spike times converge at first
+    order in dt to an independent high-accuracy ODE solution: this pins the
+    current assembly (signs, reversal potentials, units, area scaling of the
+    injected current) and the gate update order inside the time loop."""
+    j, t_end, d = 10.0, 50.0, 20.0
+    area_cm2 = math.pi * d * d * 1e-8
+    ref = hh_space_clamped_spike_times(j, t_end)
+    assert len(ref) == 4
+    isi = np.diff(ref)
+    assert np.all((isi > 14.0) & (isi < 15.2))
+    errs = []
+    for dt in (0.025, 0.0125, 0.00625):
+        prob = chain_problem(1, diam=d, length=d, mech=1, iext=j * area_cm2 * 1e3, dt=dt)
+        n = int(round(t_end / dt))
+        s = orc.Sim(prob, max_steps=n)
+        s.step(n)
+        t_sp = s.spikes()[:, 1] * dt
+        s.close()
+        assert len(t_sp) == len(ref)
+        err = t_sp - ref
+        # detection reports the step that crosses, so each time lies at most
+        # one step late on top of the scheme's O(dt) error
+        assert np.all(np.abs(err) <= 10 * dt)
+        errs.append(np.abs(err).max())
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 1.6 < coarse / fine < 2.6
+    # the FP32-gating mode crosses at the same steps, give or take one
+    prob = chain_problem(1, diam=d, length=d, mech=1, iext=j * area_cm2 * 1e3, dt=0.025,
+                         precision=1)
+    s = orc.Sim(prob, max_steps=2000)
+    s.step(2000)
+    steps32 = s.spikes()[:, 1]
+    s.close()
+    prob = chain_problem(1, diam=d, length=d, mech=1, iext=j * area_cm2 * 1e3, dt=0.025)
+    s = orc.Sim(prob, max_steps=2000)
+    s.step(2000)
+    steps64 = s.spikes()[:, 1]
+    s.close()
+    assert len(steps32) == len(steps64) == 4
+    assert np.all(np.abs(steps32 - steps64) <= 1)
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 1 against dense Gaussian elimination
 # ---------------------------------------------------------------------------
