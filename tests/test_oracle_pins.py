@@ -230,6 +230,80 @@ def test_driven_hh_compartment_converges_to_the_hh_ode(orc):
     assert np.all(np.abs(steps32 - steps64) <= 1)
 
 
+def test_active_cable_converges_to_its_method_of_lines_ode(orc):
+    """An unbranched HH cable (40 compartments of 20 um x 2 um, sealed ends,
+    0.2 nA into compartment 0) launches an action potential that propagates to
+    the far end. The semi-discrete equations (Eq. 1 per compartment: capacitive
+    current = axial currents to the neighbours through pi d^2 / (4 Ra L) +
+    injected - ionic current, with the gate ODEs) are integrated by scipy's
+    LSODA. The oracle's crossing times at both ends converge to them at first
+    order in dt, which pins the axial coupling together with the active
+    membrane."""
+    from scipy.integrate import solve_ivp
+    ch = W.CHANNELS
+    n_c, d, L, i0, t_end = 40, 2.0, 20.0, 0.2, 12.0
+    area = math.pi * d * L * 1e-8                                   # cm^2
+    g_ax = math.pi * (d * 1e-4) ** 2 / (4 * ch["ra"] * L * 1e-4) * 1e6  # uS
+    c_n = ch["cm"] * area * 1e3                                     # nF
+
+    def rates(v):
+        um, un = -(v + 40) / 10, -(v + 55) / 10
+        with np.errstate(invalid="ignore", divide="ignore"):
+            am = np.where(um == 0, 1.0, 0.1 * (v + 40) / (1 - np.exp(um)))
+            an = np.where(un == 0, 0.1, 0.01 * (v + 55) / (1 - np.exp(un)))
+        return (am, 4 * np.exp(-(v + 65) / 18), 0.07 * np.exp(-(v + 65) / 20),
+                1 / (1 + np.exp(-(v + 35) / 10)), an, 0.125 * np.exp(-(v + 65) / 80))
+
+    def rhs(t, y):
+        v, m, h, n = y.reshape(4, n_c)
+        am, bm, ah, bh, an, bn = rates(v)
+        # S/cm^2 * mV * cm^2 = mA, times 1e6 for nA
+        i_ion = 1e6 * area * (ch["gnabar"] * m ** 3 * h * (v - ch["ena"])
+                              + ch["gkbar"] * n ** 4 * (v - ch["ek"]) + ch["gl"] * (v - ch["el"]))
+        i_ax = np.zeros(n_c)
+        i_ax[:-1] += g_ax * (v[1:] - v[:-1])
+        i_ax[1:] += g_ax * (v[:-1] - v[1:])
+        i_ax[0] += i0
+        return np.concatenate([(i_ax - i_ion) / c_n, am * (1 - m) - bm * m,
+                               ah * (1 - h) - bh * h, an * (1 - n) - bn * n])
+
+    def near(t, y):
+        return y[0]
+
+    def far(t, y):
+        return y[n_c - 1]
+    near.direction = far.direction = 1
+    r = rates(np.array(-65.0))
+    y0 = np.concatenate([np.full(n_c, -65.0)] + [np.full(n_c, r[k] / (r[k] + r[k + 1]))
+                                                 for k in (0, 2, 4)])
+    sol = solve_ivp(rhs, (0.0, t_end), y0, method="LSODA", rtol=1e-9, atol=1e-10,
+                    events=[near, far])
+    assert len(sol.t_events[0]) == len(sol.t_events[1]) == 1
+    ref = np.array([sol.t_events[0][0], sol.t_events[1][0]])
+    assert 1.0 < ref[1] - ref[0] < 1.6   # about 0.6 m/s over 780 um
+
+    errs = []
+    for dt in (0.025, 0.0125, 0.00625):
+        prob = chain_problem(n_c, diam=d, length=L, mech=1, iext=i0, dt=dt)
+        steps = int(round(t_end / dt))
+        s = orc.Sim(prob, max_steps=steps)
+        prev, t_far = s.voltages()[-1], []
+        for k in range(steps):
+            s.step(1)
+            v = s.voltages()[-1]
+            if prev < 0.0 <= v:
+                t_far.append((k + 1) * dt)
+            prev = v
+        t_near = s.spikes()[:, 1] * dt
+        s.close()
+        assert len(t_near) == len(t_far) == 1
+        err = np.abs(np.array([t_near[0], t_far[0]]) - ref)
+        assert np.all(err <= 3 * dt)
+        errs.append(err[1])
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 1.6 < coarse / fine < 2.6
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 1 against dense Gaussian elimination
 # ---------------------------------------------------------------------------
