@@ -521,6 +521,43 @@ def test_single_event_conductance_is_w_q_power_k(orc):
         assert gs[first + k] == pytest.approx(w * q ** (k + 1), rel=(k + 2) * 2.3e-16)
 
 
+def test_conductances_superpose_events_across_delays(orc):
+    """Several synapses onto one passive compartment, fed from a replay
+    raster: two of them share a presynaptic neuron with different delays,
+    one receives two events, and two events land in the same step. Each
+    synapse's conductance must equal the superposition of w q^(k+1) over its
+    events (linear first-order decay, Section 2), and nothing may arrive
+    before its delay."""
+    prob = chain_problem(1, diam=10.0, length=10.0, mech=0)
+    pre = np.array([0, 1, 0, 2], np.int32)
+    delay = np.array([40, 45, 100, 41], np.int32)
+    w = np.array([0.003, 0.002, 0.001, 0.0025])
+    prob.update(syn_pre=pre, syn_post=np.zeros(4, np.int32), syn_comp=np.zeros(4, np.int32),
+                syn_delay=delay, syn_w=w)
+    steps = 300
+    raster = np.zeros((steps + 1, 3), np.uint8)
+    fired = {0: [5, 9], 1: [4], 2: [8]}   # synapses 0, 1 and 3 all deliver at step 49
+    for j, ts in fired.items():
+        raster[ts, j] = 1
+    s = orc.Sim(prob, max_steps=steps)
+    s.set_input_raster(raster)
+    q = s.q
+    gs = []
+    for _ in range(steps):
+        s.step(1)
+        gs.append(s.g())
+    s.close()
+    gs = np.array(gs)
+    for k in range(4):
+        arrivals = [t + int(delay[k]) for t in fired[int(pre[k])]]
+        for m in range(steps):
+            want = sum(w[k] * q ** (m - a + 1) for a in arrivals if m >= a)
+            if want == 0.0:
+                assert gs[m, k] == 0.0, (k, m)
+            else:
+                assert gs[m, k] == pytest.approx(want, rel=1e-13), (k, m)
+
+
 def test_spike_is_an_upward_threshold_crossing(orc):
     prob = two_neuron_chain(40, 0.0, iext0=0.25)   # ~20 uA/cm2: repetitive firing
     s = orc.Sim(prob, max_steps=3000)
