@@ -431,6 +431,105 @@ def test_cable_converges_to_continuum_at_second_order(orc):
         assert 1.9 < o < 2.1, (errs, orders)
 
 
+def diameter_step_error(orc, k):
+    """Passive sealed cable of 600 um at 2 um, then 400 um at 1 um, current
+    into the first compartment. Max deviation (mV) of the steady state from
+    the continuum solution with V and axial current continuous at the step."""
+    ch = W.CHANNELS
+    l0, l1, d0, d1, i0 = 600.0, 400.0, 2.0, 1.0, 0.02
+    n0, n1 = 12 * k, 8 * k
+    prob = chain_problem(n0 + n1, mech=0, iext=i0,
+                         lengths=np.concatenate([np.full(n0, l0 / n0), np.full(n1, l1 / n1)]),
+                         diams=np.concatenate([np.full(n0, d0), np.full(n1, d1)]))
+    s = orc.Sim(prob, max_steps=16000)
+    s.step(16000)
+    v = s.voltages() - ch["e_pas"]
+    s.close()
+    rm = 1.0 / ch["g_pas"]
+
+    def lam(d):
+        return math.sqrt(d * 1e-4 * rm / (4 * ch["ra"]))
+
+    def r_a(d):
+        return 4 * ch["ra"] / (math.pi * (d * 1e-4) ** 2)
+    x_0, x_1 = l0 * 1e-4 / lam(d0), l1 * 1e-4 / lam(d1)
+    # daughter: B cosh(x_1 - y); parent: P cosh(x_0 - x) + Q sinh(x_0 - x), with
+    # P = B cosh(x_1) (V continuous), Q = B sinh(x_1) r_a0 lam0 / (r_a1 lam1)
+    # (current continuous) and the injected current fixing the scale at x = 0
+    k1 = math.sinh(x_1) * r_a(d0) * lam(d0) / (r_a(d1) * lam(d1))
+    b = i0 * 1e-9 * r_a(d0) * lam(d0) * 1e3 / (math.cosh(x_1) * math.sinh(x_0)
+                                                + k1 * math.cosh(x_0))
+    xs = (np.arange(n0) + 0.5) * (l0 / n0) * 1e-4 / lam(d0)
+    ys = (np.arange(n1) + 0.5) * (l1 / n1) * 1e-4 / lam(d1)
+    ref = np.concatenate([b * math.cosh(x_1) * np.cosh(x_0 - xs) + b * k1 * np.sinh(x_0 - xs),
+                          b * np.cosh(x_1 - ys)])
+    return np.max(np.abs(v - ref))
+
+
+def test_diameter_step_converges_at_second_order(orc):
+    """Across a change of diameter the two half-compartment resistances in
+    series carry the axial current exactly, so the scheme keeps its second
+    order: a wrong diameter or length in either half would not."""
+    errs = [diameter_step_error(orc, k) for k in (2, 4, 8)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 1e-4
+    for o in orders:
+        assert 1.9 < o < 2.1, (errs, orders)
+
+
+def rall_tree_error(orc, k):
+    """Passive parent cylinder (600 um, d0 = 2 um) forking into two identical
+    daughters (400 um) whose diameters obey Rall's 3/2 power rule, current
+    into the parent's first compartment. Max deviation (mV) of the oracle's
+    steady state from the equivalent-cylinder solution at compartment
+    centres."""
+    ch = W.CHANNELS
+    l0, l1, d0, i0 = 600.0, 400.0, 2.0, 0.02
+    d1 = d0 * 2 ** (-2 / 3)                     # d0^(3/2) = 2 d1^(3/2)
+    n0, n1 = 12 * k, 8 * k
+    n = n0 + 2 * n1
+    parent = np.empty(n, np.int32)
+    parent[0] = -1
+    parent[1:n0] = np.arange(n0 - 1)
+    for b in range(2):
+        s0 = n0 + b * n1
+        parent[s0] = n0 - 1
+        parent[s0 + 1:s0 + n1] = np.arange(s0, s0 + n1 - 1)
+    prob = chain_problem(n, parent=parent, mech=0, iext=i0,
+                         lengths=np.concatenate([np.full(n0, l0 / n0), np.full(2 * n1, l1 / n1)]),
+                         diams=np.concatenate([np.full(n0, d0), np.full(2 * n1, d1)]))
+    s = orc.Sim(prob, max_steps=16000)
+    s.step(16000)
+    v = s.voltages() - ch["e_pas"]
+    s.close()
+    rm = 1.0 / ch["g_pas"]
+    lam0 = math.sqrt(d0 * 1e-4 * rm / (4 * ch["ra"]))
+    lam1 = math.sqrt(d1 * 1e-4 * rm / (4 * ch["ra"]))
+    r_a0 = 4 * ch["ra"] / (math.pi * (d0 * 1e-4) ** 2)
+    big_x = l0 * 1e-4 / lam0 + l1 * 1e-4 / lam1    # electrotonic length of the equivalent cylinder
+    x0 = (np.arange(n0) + 0.5) * (l0 / n0) * 1e-4 / lam0
+    x1 = l0 * 1e-4 / lam0 + (np.arange(n1) + 0.5) * (l1 / n1) * 1e-4 / lam1
+    amp = i0 * 1e-9 * r_a0 * lam0 / math.sinh(big_x) * 1e3
+    ref = amp * np.cosh(big_x - np.concatenate([x0, x1, x1]))
+    assert np.array_equal(v[n0:n0 + n1], v[n0 + n1:])   # the two daughters are one solution
+    return np.max(np.abs(v - ref)), ref[0]
+
+
+def test_branched_tree_converges_to_rall_equivalent_cylinder(orc):
+    """A fork whose daughters obey the 3/2 power rule behaves, in the
+    continuum, like one cylinder of the parent's diameter (Rall). The
+    discrete steady state converges to it as the compartments shrink. The
+    convergence is first order: each daughter couples to the parent's centre
+    through its own half-resistance plus the parent's, so the parent's last
+    half-compartment is counted once per daughter, an O(h) junction error
+    (unbranched cables converge at second order)."""
+    errs, v0 = zip(*[rall_tree_error(orc, k) for k in (2, 4, 8)])
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert errs[-1] < 1e-3 * v0[-1]
+    for o in orders:
+        assert 0.9 < o < 1.2, (errs, orders)
+
+
 def test_leak_decay_invariant_on_random_tree(orc):
     """Leak only, uniform g/cm: the axial terms cancel in the row sums, so
     sum_i C_i (V_i^{n+1} - E) = sum_i C_i (V_i^n - E) / (1 + dt g/cm)."""
