@@ -230,7 +230,8 @@ def test_driven_hh_compartment_converges_to_the_hh_ode(orc):
     assert np.all(np.abs(steps32 - steps64) <= 1)
 
 
-def test_active_cable_converges_to_its_method_of_lines_ode(orc):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_active_cable_converges_to_its_method_of_lines_ode(orc, precision):
     """An unbranched HH cable (40 compartments of 20 um x 2 um, sealed ends,
     0.2 nA into compartment 0) launches an action potential that propagates to
     the far end. The semi-discrete equations (Eq. 1 per compartment: capacitive
@@ -284,7 +285,7 @@ def test_active_cable_converges_to_its_method_of_lines_ode(orc):
 
     errs = []
     for dt in (0.025, 0.0125, 0.00625):
-        prob = chain_problem(n_c, diam=d, length=L, mech=1, iext=i0, dt=dt)
+        prob = chain_problem(n_c, diam=d, length=L, mech=1, iext=i0, dt=dt, precision=precision)
         steps = int(round(t_end / dt))
         s = orc.Sim(prob, max_steps=steps)
         prev, t_far = s.voltages()[-1], []
@@ -655,6 +656,57 @@ def test_conductances_superpose_events_across_delays(orc):
                 assert gs[m, k] == 0.0, (k, m)
             else:
                 assert gs[m, k] == pytest.approx(want, rel=1e-13), (k, m)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("e_syn", [0.0, -80.0])
+def test_postsynaptic_potential_converges_to_the_conductance_ode(orc, e_syn, precision):
+    """One event onto a passive compartment (replay raster, spike at 1 ms,
+    delay 2 ms). The membrane sees the conductance-based synaptic current
+    g(t) (V - E_syn) with g(t) = w exp(-(t - t_a)/tau) from the arrival t_a on
+    (Section 2): an EPSP of about 12 mV for E_syn = 0, an IPSP for -80 mV.
+    The oracle's voltage converges at first order in dt to scipy's LSODA
+    solution of C dV/dt = -g_pas A (V - E_pas) - g(t) (V - E_syn)."""
+    from scipy.integrate import solve_ivp
+    ch = W.CHANNELS
+    d, w, t_spk, t_del, t_end = 10.0, 0.0005, 1.0, 2.0, 30.0
+    tau = W.default_params()["tau_syn"]
+    area_cm2 = math.pi * d * d * 1e-8
+    g_m = ch["g_pas"] * area_cm2 * 1e6     # uS
+    c_n = ch["cm"] * area_cm2 * 1e3        # nF
+    t_a = t_spk + t_del
+
+    def rhs(t, y):
+        g = w * math.exp(-(t - t_a) / tau)
+        return [(-g_m * (y[0] - ch["e_pas"]) - g * (y[0] - e_syn)) / c_n]
+    ts = np.arange(4.0, t_end + 1e-9, 1.0)
+    ref = solve_ivp(rhs, (t_a, t_end), [ch["e_pas"]], method="LSODA", rtol=1e-11, atol=1e-12,
+                    t_eval=ts, first_step=1e-6).y[0]
+    if e_syn == 0.0:
+        assert 11.0 < ref.max() - ch["e_pas"] < 13.5
+    else:
+        assert -3.5 < ref.min() - ch["e_pas"] < -2.0
+    errs = []
+    for dt in (0.025, 0.0125, 0.00625):
+        prob = chain_problem(1, diam=d, length=d, mech=0, dt=dt, precision=precision)
+        prob["params"]["e_syn"] = e_syn
+        prob.update(syn_pre=np.array([0], np.int32), syn_post=np.zeros(1, np.int32),
+                    syn_comp=np.zeros(1, np.int32),
+                    syn_delay=np.array([round(t_del / dt)], np.int32), syn_w=np.array([w]))
+        steps = int(round(t_end / dt))
+        raster = np.zeros((steps + 1, 1), np.uint8)
+        raster[round(t_spk / dt), 0] = 1
+        s = orc.Sim(prob, max_steps=steps)
+        s.set_input_raster(raster)
+        v = []
+        for t in ts:
+            s.step(int(round(t / dt)) - s.step_count)
+            v.append(s.voltages()[0])
+        s.close()
+        errs.append(np.max(np.abs(np.array(v) - ref)))
+        assert errs[-1] < 2.0 * dt
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 1.8 < coarse / fine < 2.2
 
 
 def test_spike_is_an_upward_threshold_crossing(orc):
