@@ -220,8 +220,9 @@ const char *sim_config_string(const sim_t *sim);
 
 void sim_destroy(sim_t *sim);
 
-/* Description of the last failure on `sim` (or of the last failed
- * sim_create when sim is NULL). Library-owned; valid until the next call. */
+/* Description of the last failure on `sim` (or, when sim is NULL, of the
+ * calling thread's last failed call without a handle: sim_create or a cost
+ * model call). Library-owned; valid until the next call. */
 const char *sim_last_error(const sim_t *sim);
 
 /* ---------------------------------------------------------------------------

@@ -31,7 +31,9 @@ using namespace mmh;
 
 namespace {
 
-std::string g_create_error;
+// Failure text of calls without a simulation handle (sim_create, the cost
+// model calls); one per calling thread, so concurrent callers do not race.
+thread_local std::string g_create_error;
 
 struct Error {
     int code;

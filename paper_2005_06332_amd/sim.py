@@ -86,6 +86,16 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_2005_06332_amd/build.py "
                               "(or __graft_entry__.build()) first")
+        # One HIP runtime per process. torch ships its own copy of the HIP
+        # and ROCr runtimes under the same sonames the library depends on;
+        # loaded after torch, the library binds to torch's copy, so streams
+        # and device pointers from torch are valid in it. Loaded before
+        # torch, the process would end up with two runtimes, and whichever
+        # initialises second can find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.sim_default_params.argtypes = [C.POINTER(Params)]

@@ -103,3 +103,29 @@ def test_valid_problem_without_gpu_reports_no_device(S):
     with pytest.raises(S.SimError) as e:
         S.Simulation(W.mini(n_neurons=8, n_steps=40))
     assert e.value.code == S.SIM_EDEVICE
+
+
+def test_failure_text_is_per_thread(S):
+    """Failures without a handle keep their text per calling thread: two
+    threads failing sim_create for different reasons each read their own."""
+    import threading
+    prob = W.mini(n_neurons=12, n_steps=40)
+    cases = [(dict(threads=100), "threads must be"), (dict(solver=5), "unknown solver")]
+    bad = []
+
+    def worker(kw, want):
+        for _ in range(200):
+            try:
+                S.Simulation(prob, **kw)
+            except S.SimError as e:
+                if want not in str(e):
+                    bad.append(str(e))
+            else:
+                bad.append("no error")
+
+    ts = [threading.Thread(target=worker, args=c) for c in cases]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not bad, bad[:3]
