@@ -129,3 +129,22 @@ def test_failure_text_is_per_thread(S):
     for t in ts:
         t.join()
     assert not bad, bad[:3]
+
+
+def test_one_hip_runtime_per_process():
+    """Loading the library and then torch leaves a single HIP runtime (and a
+    single ROCr runtime) mapped in the process: the binding brings torch in
+    first, so the library binds to torch's copy."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2005_06332_amd import sim\n"
+        "sim.lib()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().split()\n"
+        "print(len({m for m in maps if 'libamdhip64' in m}),"
+        " len({m for m in maps if 'libhsa-runtime64' in m}))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300, check=True).stdout.split()
+    assert out == ["1", "1"], out
