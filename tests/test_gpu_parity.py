@@ -123,6 +123,16 @@ def test_variable_delays_match(S, orc):
     compare("mini delays 40..200", v, vr, s, sr)
 
 
+@pytest.mark.parametrize("e_syn,precision", [(-80.0, 1), (20.0, 0)])
+def test_synaptic_reversal_potential_matches(S, orc, e_syn, precision):
+    """E_syn = 0 mV makes the synaptic driving term g E_syn vanish; an
+    inhibitory (-80 mV) and a positive (+20 mV) reversal exercise it."""
+    prob = W.mini(seed=29, n_steps=240, n_neurons=48)
+    prob["params"]["e_syn"] = e_syn
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 240, precision)
+    compare(f"mini E_syn={e_syn} prec={precision}", v, vr, s, sr)
+
+
 def test_epoch_shorter_than_delay_matches(S, orc):
     prob = W.mini(seed=19, n_steps=200, n_neurons=40)
     (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 200, 0, epoch_steps=13)
