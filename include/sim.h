@@ -26,6 +26,10 @@
  *  - neuron ids and compartment order are always the caller's input order,
  *    never the library's internal (packed) order;
  *  - calls on one sim_t are not thread-safe; distinct sim_t are independent;
+ *  - the library uses the HIP runtime the process has loaded under the soname
+ *    libamdhip64.so.7; a stream passed in (sim_params_t.hip_stream) must come
+ *    from that same runtime, so a host that brings its own copy (as torch
+ *    does) loads it before this library;
  *  - results (voltages, spikes) are bitwise independent of the packing mode,
  *    the autotuner and the cost model.
  */
