@@ -61,6 +61,14 @@ MUTANTS = [
      "o->G[b + i] = 1.0 / (rhalf[b + i] + rhalf[b + parent[b + i]]);",
      "o->G[b + i] = 1.0 / (rhalf[b + i] + rhalf[b + i]);",
      P.test_diameter_step_converges_at_second_order, {}),
+    ("implicit axial weight 1 instead of theta",
+     "o->e[b + i] = -P->theta * o->G[b + i];",
+     "o->e[b + i] = -o->G[b + i];",
+     P.test_axial_time_stepping_order, dict(theta=0.5, order=2.0)),
+    ("explicit axial weight 1 instead of 1 - theta",
+     "    const double omt = 1.0 - P->theta;",
+     "    const double omt = 1.0;",
+     P.test_axial_time_stepping_order, dict(theta=0.5, order=2.0)),
     ("float path: leak reversal E_L -> E_K",
      "jion = (gna * ena + gk * ek) + gl * el;",
      "jion = (gna * ena + gk * ek) + gl * ek;",

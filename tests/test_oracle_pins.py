@@ -432,6 +432,41 @@ def test_cable_converges_to_continuum_at_second_order(orc):
         assert 1.9 < o < 2.1, (errs, orders)
 
 
+@pytest.mark.parametrize("theta,order", [(0.5, 2.0), (1.0, 1.0)])
+def test_axial_time_stepping_order(orc, theta, order):
+    """With no membrane conductance the step is the theta-method on the
+    cable's linear axial system C dV/dt = -K V: Crank-Nicolson (theta = 1/2,
+    the factor 2 of Eq. 2) is second order in dt, backward Euler (theta = 1)
+    first order. The reference is the exact solution exp(-C^-1 K t) V0 of the
+    semi-discrete system, with K built from the geometry."""
+    from scipy.linalg import expm
+    ch = W.CHANNELS
+    n, d, L, t_end = 30, 2.0, 20.0, 2.0
+    g_ax = math.pi * (d * 1e-4) ** 2 / (4 * ch["ra"] * L * 1e-4) * 1e6   # uS
+    c_n = ch["cm"] * math.pi * d * L * 1e-8 * 1e3                        # nF
+    K = np.zeros((n, n))
+    for i in range(1, n):
+        K[i, i] += g_ax
+        K[i - 1, i - 1] += g_ax
+        K[i, i - 1] -= g_ax
+        K[i - 1, i] -= g_ax
+    x = (np.arange(n) + 0.5) / n
+    v0 = ch["e_pas"] + 10.0 * np.cos(math.pi * x) + 5.0 * np.cos(2 * math.pi * x)
+    ref = ch["e_pas"] + expm(-K / c_n * t_end) @ (v0 - ch["e_pas"])
+    errs = []
+    for dt in (0.05, 0.025, 0.0125):
+        prob = chain_problem(n, diam=d, length=L, mech=0, dt=dt)
+        prob["channels"]["g_pas"] = 0.0
+        prob["params"]["theta"] = theta
+        s = orc.Sim(prob, max_steps=200)
+        s.set_voltages(v0)
+        s.step(int(round(t_end / dt)))
+        errs.append(np.max(np.abs(s.voltages() - ref)))
+        s.close()
+    for coarse, fine in zip(errs, errs[1:]):
+        assert abs(math.log2(coarse / fine) - order) < 0.05, errs
+
+
 def diameter_step_error(orc, k):
     """Passive sealed cable of 600 um at 2 um, then 400 um at 1 um, current
     into the first compartment. Max deviation (mV) of the steady state from
