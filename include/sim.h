@@ -158,48 +158,74 @@ typedef struct {
     int32_t step;   /* spike happened during the transition step-1 -> step */
 } sim_spike_t;
 
-/* Fill *p with defaults (FP32 gating, COUNT packing, autotune off). */
+/* Fill *p with defaults (FP32 gating, COUNT packing, autotune off).
+ * Source: the numerical parameters of Eq. 2 (dt, theta) and of Section 2's
+ * two-level stepping; the remaining fields are launch options of this library. */
 void sim_default_params(sim_params_t *p);
 
 /* Validate the network, lay it out on the device, compute the time-invariant
  * coefficients on the GPU and initialise the state (V = v_init, gates at
  * steady state, conductances 0). Every validation failure is reported before
- * any device allocation. On success *out owns the simulation. */
+ * any device allocation. On success *out owns the simulation.
+ * Source: the problem as Section 2 states it: neurons with their parent
+ * vectors p (Hines-matrix paragraph), the coefficients of Eq. 2 that do not
+ * change in time (off-diagonals from the geometry), synapses with a network
+ * delay (local/global steps). */
 int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
                const sim_channels_t *channels, const sim_synapses_t *syn,
                sim_t **out);
 
 /* Advance by n_steps (>= 0) time steps; returns when the work is complete
- * on the device. */
+ * on the device, with the steps' spikes recorded (see sim_spikes).
+ * Source: one local step of Section 2 per time step: delivery, the current
+ * I of Eq. 1, assembly of Eq. 2, Algorithm 1, then spike detection (the
+ * paragraph after Algorithm 1); spikes reach their targets after their
+ * delay (the local and global buffers of Section 2.1). Device memory does
+ * not grow with the number of steps. */
 int sim_step(sim_t *sim, int64_t n_steps);
 
-/* Steps simulated so far. */
+/* Steps simulated so far (local steps dt of Section 2). */
 int64_t sim_time_steps(const sim_t *sim);
 
-/* Membrane voltages (mV) of every compartment, input order; cap >= total. */
+/* Membrane voltages (mV) of every compartment, input order; cap >= total.
+ * Source: the unknowns V of Eq. 2 (the solution of Algorithm 1's forward
+ * sweep) after the last step. */
 int sim_read_voltages(sim_t *sim, double *out_mV, int64_t cap);
 
-/* Gate states (m, h, n) of every compartment as double, input order. */
+/* Gate states (m, h, n) of every compartment as double, input order.
+ * Source: the state behind the membrane current I of Eq. 1 (the paper
+ * names no channel model; the Hodgkin-Huxley reading is this library's). */
 int sim_read_gates(sim_t *sim, double *m, double *h, double *n, int64_t cap);
 
-/* Synaptic conductances (uS), synapse id order. */
+/* Synaptic conductances (uS), synapse id order.
+ * Source: the per-synapse work of Section 2 (the S term of the operation
+ * count per global step). */
 int sim_read_conductances(sim_t *sim, double *out_uS, int64_t cap);
 
 /* All spikes so far, sorted by (step, neuron). *n_total always receives the
  * count; out == NULL only queries it; SIM_EINVAL if cap is too small
- * (nothing written then). */
+ * (nothing written then).
+ * Source: Section 2, the paragraph after Algorithm 1 (a spike is a threshold
+ * crossing of the voltage) and the spike events stored per global step. */
 int sim_spikes(sim_t *sim, sim_spike_t *out, int64_t cap, int64_t *n_total);
 
 /* Per-neuron kernel time in nanoseconds accumulated since create (or since
  * the last reset), when record_timings is on. A neuron sharing a pack with
- * others is charged the pack time split in proportion to compartments. */
+ * others is charged the pack time split in proportion to compartments.
+ * Source: not a call the paper defines; it feeds the learned cost model of
+ * the benchmark specification (trained on per-neuron timings), the analogue
+ * of the per-task traces of Section 3's performance analysis. */
 int sim_neuron_timings(sim_t *sim, double *out_ns, int64_t cap, int32_t reset);
 
 /* The 16 morphology features of every neuron (input order, row-major
- * [n_neurons][16], float) that the cost model consumes. */
+ * [n_neurons][16], float) that the cost model consumes.
+ * Source: the benchmark specification's cost model inputs (compartment
+ * count, depth, branch count, longest branch, ...); the paper itself uses
+ * only the size (Section 4, sorting by size). */
 int sim_features(sim_t *sim, float *out, int64_t cap);
 
-/* Launch timing, off by default. While on, sim_step records HIP events on
+/* Launch timing, off by default. Source: measurement call of this library
+ * (not defined by the paper). While on, sim_step records HIP events on
  * the simulator's stream around each graph replay (or directly launched
  * epoch), and sim_step reads them back before it returns. Each size-class
  * launch also times itself on the device: the span from a one-thread stamp
@@ -211,22 +237,27 @@ int sim_features(sim_t *sim, float *out, int64_t cap);
  * totals. */
 int sim_set_kernel_timing(sim_t *sim, int32_t on);
 /* Total device time (ms) of the epochs (fork to join of the concurrent
- * size-class launches) and their count. */
+ * size-class launches) and their count.
+ * Source: measurement call of this library (not defined by the paper). */
 int sim_kernel_time(sim_t *sim, double *ms, int64_t *launches);
 /* For size class cls (0..2, 0 = the smallest LDS budget, normally holding
  * most packs): total device time (ms) of its launches (stamp before the
  * launch to its last workgroup's end), their count, and the compartments the class
- * advances per step. Any output may be NULL. */
+ * advances per step. Any output may be NULL.
+ * Source: measurement call of this library (not defined by the paper). */
 int sim_class_time(sim_t *sim, int32_t cls, double *ms, int64_t *launches, int64_t *comps);
 
-/* Launch configuration actually used (after autotuning), as text. */
+/* Launch configuration actually used (after autotuning), as text.
+ * Source: measurement call of this library (not defined by the paper). */
 const char *sim_config_string(const sim_t *sim);
 
+/* Release the simulation and its device memory. */
 void sim_destroy(sim_t *sim);
 
 /* Description of the last failure on `sim` (or, when sim is NULL, of the
  * calling thread's last failed call without a handle: sim_create or a cost
- * model call). Library-owned; valid until the next call. */
+ * model call). Library-owned; valid until the next call.
+ * Source: error reporting of this library (not defined by the paper). */
 const char *sim_last_error(const sim_t *sim);
 
 /* ---------------------------------------------------------------------------

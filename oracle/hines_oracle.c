@@ -199,22 +199,38 @@ void orc_gates_update_f(float v, float dt, float *m, float *h, float *n)
 }
 
 /* ---------------------------------------------------------------------- */
-/* Algorithm 1, general form: a = upper (A[p(i), i]), b = diagonal,        */
-/* c = lower (A[i, p(i)]). Overwrites b and rhs; rhs returns the solution. */
+/* Linear solve on a tree-structured matrix (the system of Eq. 2).         */
 /* ---------------------------------------------------------------------- */
 
-void orc_hines_solve(int32_t n, const int32_t *p, const double *a, double *b,
-                     const double *c, double *rhs)
+/* Solves A x = rhs where the only off-diagonal entries of A link each
+ * compartment k >= 1 with its parent up = parent[k] < k:
+ *   to_parent[k]   = A[up][k]  (the entry in the parent's row),
+ *   from_parent[k] = A[k][up]  (the entry in row k).
+ * Since every parent index is smaller than its child's, Gaussian elimination
+ * of the rows in descending index order only modifies rows not yet
+ * eliminated and creates no fill: eliminating row k subtracts
+ * (A[up][k] / A[k][k]) times row k from row up, which changes A[up][up] and
+ * rhs[up] only. Substitution then runs from the root outwards. This is the
+ * method of Algorithm 1; several children of one parent reach the parent's
+ * row in descending index order. diag and rhs are overwritten (the eliminated
+ * diagonal, the reduced right-hand side); x receives the solution and may be
+ * the same array as rhs. */
+void orc_tree_solve(int32_t n, const int32_t *parent, const double *to_parent,
+                    double *diag, const double *from_parent, double *rhs,
+                    double *x)
 {
-    for (int32_t i = n - 1; i >= 1; --i) {
-        double factor = a[i] / b[i];
-        b[p[i]] -= factor * c[i];
-        rhs[p[i]] -= factor * rhs[i];
+    int32_t k = n;
+    while (--k >= 1) {
+        const int32_t up = parent[k];
+        const double mult = to_parent[k] / diag[k];
+        diag[up] = diag[up] - mult * from_parent[k];
+        rhs[up] = rhs[up] - mult * rhs[k];
     }
-    rhs[0] /= b[0];
-    for (int32_t i = 1; i < n; ++i) {
-        rhs[i] -= c[i] * rhs[p[i]];
-        rhs[i] /= b[i];
+    if (n < 1) return;
+    x[0] = rhs[0] / diag[0];
+    for (k = 1; k < n; ++k) {
+        const double known = from_parent[k] * x[parent[k]];
+        x[k] = (rhs[k] - known) / diag[k];
     }
 }
 
@@ -515,8 +531,9 @@ static void neuron_step_d(orc_sim_t *o, int32_t j, int tid)
         r[i] = (o->cdt[b + i] * V[i] + r[i]) + omt * ax[i];
     }
 
-    /* 5. Hines solve (Algorithm 1) with a = c = e (symmetric) */
-    orc_hines_solve(n, p, o->e + b, d, o->e + b, r);
+    /* 5. tree solve (Algorithm 1); the matrix is symmetric, both
+     *    off-diagonals of a parent link are e */
+    orc_tree_solve(n, p, o->e + b, d, o->e + b, r, r);
 
     /* 6. gates at V^{n+1} (exponential Euler); then commit V */
     const double dt = P->dt;
@@ -597,7 +614,7 @@ static void neuron_step_f(orc_sim_t *o, int32_t j, int tid)
         r[i] = (o->cdt[b + i] * V[i] + r[i]) + omt * ax[i];
     }
 
-    orc_hines_solve(n, p, o->e + b, d, o->e + b, r);
+    orc_tree_solve(n, p, o->e + b, d, o->e + b, r, r);
 
     const float dt = (float)P->dt;
     const int32_t det = o->detector[j];

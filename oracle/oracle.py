@@ -58,7 +58,7 @@ def lib():
         L.orc_exprelr_f.argtypes = [C.c_float]
         L.orc_rates_d.argtypes = [C.c_double, P]
         L.orc_rates_f.argtypes = [C.c_float, P]
-        L.orc_hines_solve.argtypes = [C.c_int32, P, P, P, P, P]
+        L.orc_tree_solve.argtypes = [C.c_int32, P, P, P, P, P, P]
         L.orc_gates_update_d.argtypes = [C.c_double, C.c_double, P, P, P]
         L.orc_gates_update_f.argtypes = [C.c_float, C.c_float, P, P, P]
         L.orc_create.restype = P
@@ -132,13 +132,14 @@ def gates_update(v, dt, m, h, n, precision: int = 0):
 
 
 def hines_solve(p, a, b, c, rhs) -> np.ndarray:
-    """Algorithm 1 on (a upper, b diagonal, c lower, rhs); returns x."""
+    """Tree solve (the method of Algorithm 1) of the matrix with diagonal b,
+    a[i] = A[p[i], i] and c[i] = A[i, p[i]]; returns x."""
     p = np.ascontiguousarray(p, np.int32)
     a = np.ascontiguousarray(a, np.float64)
     b = np.array(b, np.float64)
     c = np.ascontiguousarray(c, np.float64)
     r = np.array(rhs, np.float64)
-    lib().orc_hines_solve(len(r), _ptr(p), _ptr(a), _ptr(b), _ptr(c), _ptr(r))
+    lib().orc_tree_solve(len(r), _ptr(p), _ptr(a), _ptr(b), _ptr(c), _ptr(r), _ptr(r))
     return r
 
 
