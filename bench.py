@@ -23,10 +23,8 @@ sys.path.insert(0, ROOT)
 
 from paper_2005_06332_amd import workload as W  # noqa: E402
 
-PEAK_HBM_GBS = 8000.0
-# Non-packed vector FMA rate: 256 CUs x 64 lanes x 2 flop x 2.4 GHz. Packed
-# FP32 is not used, so float and double arithmetic share this peak.
-PEAK_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "compartment-updates/s at 1 GPU (multi-morphology) + % HBM roofline vs plain packing"
 
 # Algorithmic bytes per compartment-update of a per-step streaming update
 # (state V f64 read+write 16 B, gates read+write 24 B in FP32 / 48 B in FP64,
@@ -37,19 +35,6 @@ def bytes_per_update(precision: int, multi: bool, syn_per_comp: float) -> float:
     const = 24.0 if multi else 0.0
     g = syn_per_comp * (8.0 if precision == 1 else 16.0)
     return 16.0 + gates + const + g
-
-
-# Floating-point operations per compartment-update as the path evaluates them
-# (each exp is a Cody-Waite reduction plus a Taylor polynomial: 1 mul, 2 fma,
-# 7 fma in float / 13 in double, 1 scaling mul; fma = 2 flops).
-def flops_per_update(precision: int) -> float:
-    exp_f = 1 + 4 + (14 if precision == 1 else 26) + 1
-    rates = 6 * 2 + 6 * exp_f + 2 + 4 + 1 + 1 + 1  # 6 rates: argument, exp, scaling
-    gates = 3 * (exp_f + 6)
-    current = 21
-    assembly = 10
-    sweep = 8
-    return float(rates + gates + current + assembly + sweep)
 
 
 def kernel_source_hash() -> str:
@@ -104,6 +89,57 @@ def time_run(S, prob, steps, warmup, packing, cost_model=None, autotune=True, st
     return g, ms
 
 
+def host_info() -> dict:
+    """CPU model, logical CPUs usable by this process and RAM of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ram = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return dict(host_cpu=model, host_logical_cpus=ncpu, host_ram_gib=ram)
+
+
+def copy_bandwidth(stream) -> float:
+    """HBM bandwidth of a plain device copy (1 GiB read + 1 GiB written), GB/s:
+    the best of 5 timed copies after a warm-up copy."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = None
+    with torch.cuda.stream(stream):
+        b.copy_(a)
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            b.copy_(a)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+    del a, b
+    torch.cuda.synchronize()
+    return 2.0 * 4 * n / (best / 1e3) / 1e9
+
+
 def cpu_baseline(prob: dict, target_s: float = 15.0):
     """The oracle on a bounded sample of the same workload: the first neurons
     of the network (with the synapses among them) for a short run."""
@@ -132,7 +168,7 @@ def cpu_baseline(prob: dict, target_s: float = 15.0):
     el = time.perf_counter() - t0
     upd = float(sample["comp_off"][-1]) * steps
     return dict(value=upd / el, unit="compartment-updates/s", cores=O.num_threads(),
-                kind="oracle",
+                kind="oracle", **host_info(),
                 sample=f"first {nn} neurons of {prob['name']} ({int(sample['comp_off'][-1])} "
                        f"compartments, synapses among them), {steps} steps, {el:.1f} s, "
                        f"precision mode {prob['params']['precision']}")
@@ -148,15 +184,17 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="override the workload's precision (fp32 = FP32 gating, FP64 Hines)")
     ap.add_argument("--packing", default="count", choices=["plain", "count", "learned"])
-    ap.add_argument("--solver", default="fast", choices=["exact", "fast"],
+    ap.add_argument("--solver", default="fast", choices=["exact", "fast", "contract"],
                     help="exact: the elimination in the reference operation order (bitwise "
-                         "equal to the CPU oracle); fast: division-free homogeneous form")
+                         "equal to the CPU oracle); fast: division-free homogeneous form; "
+                         "contract: tree contraction")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-packing comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed run, copy 1 GiB with a plain copy kernel (reference "
                          "for the HBM byte counters)")
+    ap.add_argument("--no-kbw", action="store_true", help="skip the copy-bandwidth probe")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -180,7 +218,7 @@ def main():
     if packing == S.PACK_LEARNED:
         cost_model = costmodel.load_or_train(prob)
 
-    solver = S.SOLVE_FAST if args.solver == "fast" else S.SOLVE_EXACT
+    solver = dict(exact=S.SOLVE_EXACT, fast=S.SOLVE_FAST, contract=S.SOLVE_CONTRACT)[args.solver]
     g, ms = time_run(S, prob, args.steps, args.warmup, packing, cost_model,
                      autotune=not args.no_autotune, stream=stream, solver=solver)
     config_str = g.config
@@ -209,26 +247,33 @@ def main():
 
     syn_per_comp = prob["syn_pre"].shape[0] / C
     b_alg = bytes_per_update(prec, multi, syn_per_comp)
-    k_ms, k_n, k_comps = cls[0]
+    # the dominant kernel: the size-class-0 launch; its units are the
+    # compartment-updates its launches performed over the timed region
+    # (class compartments x the steps each launch ran), its time the launches'
+    # own device spans
+    k_ms, k_n, k_comps, k_upd = cls[0]
     kernel_ms = k_ms / max(k_n, 1)
-    upd_per_launch = float(k_comps) * E
+    upd_per_launch = k_upd / max(k_n, 1)
+    steps_per_launch = upd_per_launch / max(k_comps, 1)
     achieved_gbs = b_alg * upd_per_launch / (kernel_ms / 1e3) / 1e9
-    flops = flops_per_update(prec)
-    achieved_tf = flops * upd_per_launch / (kernel_ms / 1e3) / 1e12
+    kbw = None if args.no_kbw else copy_bandwidth(stream)
 
     # HBM bytes per launch measured with rocprofv3 counters on this kernel
     # source (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known
-    # size); reported only while the kernel source is unchanged.
+    # size); reported only while the kernel source is unchanged and for a
+    # launch of the profiled length.
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{prob['name']}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             rec = json.load(f)
-        if rec.get("kernel_source_sha1") == kernel_source_hash():
+        if (rec.get("kernel_source_sha1") == kernel_source_hash()
+                and abs(rec.get("steps_per_launch", -1) - steps_per_launch) < 1e-9
+                and rec.get("solver") == args.solver and rec.get("packing") == args.packing):
             traffic = rec.get("bytes_per_launch")
 
     out = {
-        "metric": "compartment-updates/s at 1 GPU (multi-morphology)",
+        "metric": METRIC,
         "value": value,
         "unit": "compartment-updates/s",
         "n_gpus": 1,
@@ -247,26 +292,29 @@ def main():
             "packing": args.packing, "solver": args.solver, "launch": config_str,
             "plain_packing_value": plain,
             "speedup_vs_plain_packing": (value / plain) if plain else None,
-            "hbm_roofline_frac_streaming": value * b_alg / (PEAK_HBM_GBS * 1e9),
+            "hbm_roofline_frac_whole_run": value * b_alg / (PEAK_HBM_GBS * 1e9),
+            "plain_packing_hbm_roofline_frac": (plain * b_alg / (PEAK_HBM_GBS * 1e9)
+                                                if plain else None),
         },
         "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tf,
-            "peak": PEAK_VALU_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tf / PEAK_VALU_TFLOPS,
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / PEAK_HBM_GBS,
             "traffic": traffic,
             "kernel": "k_epoch, size class 0 launch",
+            "algorithmic_bytes_per_update": b_alg,
+            "updates_per_launch": upd_per_launch,
+            "steps_per_launch": steps_per_launch,
+            "compartments_per_launch_step": k_comps,
             "kernel_ms": kernel_ms,
             "kernel_launches": k_n,
-            "compartments_per_launch_step": k_comps,
-            "updates_per_launch": upd_per_launch,
+            "k_bw_GBps": kbw,
+            "frac_of_k_bw": (achieved_gbs / kbw) if kbw else None,
             "epoch_ms": epoch_ms / max(epochs, 1),
             "class_ms": [c[0] / max(c[1], 1) for c in cls],
             "class_compartments": [c[2] for c in cls],
-            "flops_per_update": flops,
-            "streaming_bytes_per_update": b_alg,
-            "streaming_hbm_GBps": achieved_gbs,
         },
     }
     if not args.no_cpu:

@@ -59,6 +59,11 @@ extern "C" {
                                homogeneous form: one fused multiply-add per
                                compartment on each dependent chain; agrees
                                with the exact order to rounding */
+#define SIM_SOLVE_CONTRACT 2 /* the same linear system (Eq. 2) eliminated by
+                               parallel tree contraction: rounds of
+                               compartments of degree <= 2, at least three
+                               apart, then back substitution in reverse;
+                               agrees with the exact order to rounding */
 
 #define SIM_PACK_PLAIN 0    /* neurons in input order, one workgroup per pack,
                                hardware dispatch order */
@@ -125,7 +130,7 @@ typedef struct {
     double v_thresh_mV;  /* spike when V crosses it upward at the detector */
     double v_init_mV;    /* initial voltage; gates start at steady state */
     int32_t precision;   /* SIM_FP64 | SIM_FP32_GATING */
-    int32_t solver;      /* SIM_SOLVE_EXACT | SIM_SOLVE_FAST */
+    int32_t solver;      /* SIM_SOLVE_EXACT | SIM_SOLVE_FAST | SIM_SOLVE_CONTRACT */
     int32_t packing;     /* SIM_PACK_* */
     int32_t sched;       /* SIM_SCHED_* */
     int32_t epoch_steps; /* 0: min(delay) capped at 64; else 1..min(delay),
@@ -174,6 +179,62 @@ void sim_default_params(sim_params_t *p);
 int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
                const sim_channels_t *channels, const sim_synapses_t *syn,
                sim_t **out);
+
+/* ---------------------------------------------------------------------------
+ * Layout planning and introspection (host only). Source: the load-balancing
+ * step of Section 4 (neurons sorted by size before they are scheduled) and
+ * this library's packing of neurons into workgroups; the contraction
+ * schedule is the elimination order of the solver SIM_SOLVE_CONTRACT for the
+ * matrix of Eq. 2.
+ * ------------------------------------------------------------------------- */
+
+/* Validate and lay out the problem exactly as sim_create would for a device
+ * with `lds_bytes_per_cu` bytes of LDS per compute unit and `n_cu` compute
+ * units, without any device call: packing, size classes, workgroup lists
+ * and (for SIM_SOLVE_CONTRACT) elimination schedules. The result answers
+ * the introspection calls below and sim_config_string; calls that need
+ * device state return SIM_ESTATE. Autotuning and learned packing with a
+ * cost model need the device and are refused (SIM_EINVAL). */
+int sim_plan_create(const sim_params_t *params, const sim_morphology_t *morph,
+                    const sim_channels_t *channels, const sim_synapses_t *syn,
+                    int32_t lds_bytes_per_cu, int32_t n_cu, sim_t **out);
+
+typedef struct {
+    int32_t first_position; /* position of the pack's first neuron in the
+                               packed neuron order */
+    int32_t n_neurons, n_comp, n_syn, n_branches;
+    int32_t size_class;     /* 0..2: the launch that runs the pack */
+    int32_t in_global;      /* 1: state in global scratch, tables in LDS */
+    int32_t n_rounds;       /* contraction rounds (0 for the other solvers) */
+    int32_t n_levels;       /* height levels + depth levels + 2 */
+    int32_t n_child_entries; /* child-branch list entries */
+    int64_t table_bytes;    /* LDS bytes of the pack's tables */
+    int64_t state_bytes;    /* bytes of its state (LDS unless in_global) */
+    double cost;            /* packing cost (compartments, or predicted time) */
+} sim_pack_info_t;
+
+/* Number of packs (workgroup units of work). */
+int32_t sim_pack_count(const sim_t *sim);
+/* Description of pack `pack` (0 .. count-1). */
+int sim_pack_info(const sim_t *sim, int32_t pack, sim_pack_info_t *out);
+/* Input ids of the pack's neurons, in their order inside the pack. */
+int sim_pack_neurons(const sim_t *sim, int32_t pack, int32_t *ids, int64_t cap);
+/* Workgroups, threads per workgroup and dynamic LDS bytes of size class cls
+ * (0..2); any output may be NULL. */
+int sim_class_launch(const sim_t *sim, int32_t cls, int32_t *n_wg, int32_t *threads,
+                     int64_t *lds_bytes);
+/* Packs that workgroup `wg` of class `cls` runs, in order; *n receives the
+ * count; packs == NULL only queries it. */
+int sim_workgroup_packs(const sim_t *sim, int32_t cls, int32_t wg, int32_t *packs,
+                        int64_t cap, int32_t *n);
+/* Elimination schedule of neuron `neuron` (input id) under
+ * SIM_SOLVE_CONTRACT (SIM_ESTATE otherwise): items[4q .. 4q+3] = (k, n1, n2,
+ * n1_is_parent) for the q-th eliminated compartment, neuron-local, -1 for an
+ * absent neighbour; round r spans items round_off[r] .. round_off[r+1]-1.
+ * cap >= 4 * compartments, cap_rounds >= rounds + 1; items == NULL only
+ * queries *n_rounds. */
+int sim_contraction_schedule(const sim_t *sim, int32_t neuron, int32_t *items, int64_t cap,
+                             int32_t *round_off, int64_t cap_rounds, int32_t *n_rounds);
 
 /* Advance by n_steps (>= 0) time steps; returns when the work is complete
  * on the device, with the steps' spikes recorded (see sim_spikes).
@@ -242,10 +303,12 @@ int sim_set_kernel_timing(sim_t *sim, int32_t on);
 int sim_kernel_time(sim_t *sim, double *ms, int64_t *launches);
 /* For size class cls (0..2, 0 = the smallest LDS budget, normally holding
  * most packs): total device time (ms) of its launches (stamp before the
- * launch to its last workgroup's end), their count, and the compartments the class
- * advances per step. Any output may be NULL.
+ * launch to its last workgroup's end), their count, the compartments the class
+ * advances per step, and the compartment-updates its timed launches performed
+ * (compartments x the steps each launch ran). Any output may be NULL.
  * Source: measurement call of this library (not defined by the paper). */
-int sim_class_time(sim_t *sim, int32_t cls, double *ms, int64_t *launches, int64_t *comps);
+int sim_class_time(sim_t *sim, int32_t cls, double *ms, int64_t *launches, int64_t *comps,
+                   int64_t *updates);
 
 /* Launch configuration actually used (after autotuning), as text.
  * Source: measurement call of this library (not defined by the paper). */

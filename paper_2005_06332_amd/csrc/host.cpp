@@ -108,6 +108,111 @@ void analyse(const int32_t *p, int32_t n, NeuronTopo &t) {
     t.max_depth = *std::max_element(t.depth.begin(), t.depth.end());
 }
 
+// ---------------------------------------------------------------------------
+// Elimination schedule of the contraction solver for one neuron.
+//
+// The tree system is solved by Gaussian elimination in an order that
+// contracts the tree in rounds (parallel tree contraction, Miller and Reif:
+// "rake" leaves and "compress" chains). A round eliminates a set of
+// compartments of current degree <= 2 whose pairwise distance in the current
+// tree is at least 3, so that every surviving compartment has at most one
+// eliminated neighbour in the round: one barrier per round suffices, and each
+// update of a survivor has a single writer. Eliminating k with neighbours n1,
+// n2 adds -A[n,k]^2/A[k,k] to each neighbour's diagonal, -A[n,k] r_k/A[k,k]
+// to its right-hand side, and, when both exist, links n1 and n2 with the
+// coupling -A[n1,k] A[k,n2]/A[k,k] (n2 becomes a child of n1). Back
+// substitution visits the rounds in reverse. The order depends only on the
+// neuron's parent vector, so results do not depend on packing.
+// ---------------------------------------------------------------------------
+struct Elim {
+    int32_t k, n1, n2;  // neuron-local; n1 / n2 = -1 when absent
+    bool n1_parent;     // n1 is k's current parent (else a child, or absent)
+};
+
+void contraction_schedule(const int32_t *p, int32_t n, std::vector<Elim> &items,
+                          std::vector<int32_t> &round_off) {
+    items.clear();
+    round_off.assign(1, 0);
+    std::vector<int32_t> cp(p, p + n), fc(n, -1), ns(n, -1), ps(n, -1), nch(n, 0), stamp(n, 0);
+    auto link = [&](int32_t c, int32_t par) {  // c becomes the first child of par
+        cp[c] = par;
+        ps[c] = -1;
+        ns[c] = fc[par];
+        if (fc[par] >= 0) ps[fc[par]] = c;
+        fc[par] = c;
+        nch[par]++;
+    };
+    auto unlink = [&](int32_t c) {  // detach c from its parent
+        const int32_t par = cp[c];
+        if (ps[c] >= 0) ns[ps[c]] = ns[c]; else fc[par] = ns[c];
+        if (ns[c] >= 0) ps[ns[c]] = ps[c];
+        nch[par]--;
+        cp[c] = -1;
+        ps[c] = ns[c] = -1;
+    };
+    for (int32_t i = n - 1; i >= 1; --i) link(i, p[i]);  // children in ascending order
+    std::vector<int32_t> alive(n), next, sel;
+    for (int32_t i = 0; i < n; ++i) alive[i] = n - 1 - i;  // descending index
+    int32_t round = 0;
+    auto deg = [&](int32_t v) { return nch[v] + (cp[v] >= 0 ? 1 : 0); };
+    auto mark = [&](int32_t v) {  // v and every compartment within distance 2
+        auto mark1 = [&](int32_t u) {
+            stamp[u] = round;
+            if (cp[u] >= 0) stamp[cp[u]] = round;
+            for (int32_t c = fc[u]; c >= 0; c = ns[c]) stamp[c] = round;
+        };
+        mark1(v);
+        if (cp[v] >= 0) mark1(cp[v]);
+        for (int32_t c = fc[v]; c >= 0; c = ns[c]) mark1(c);
+    };
+    while (!alive.empty()) {
+        ++round;
+        sel.clear();
+        for (int pass = 0; pass < 2; ++pass)  // leaves (and lone roots) first, then chains
+            for (int32_t v : alive) {
+                if (stamp[v] == round) continue;
+                const int d = deg(v);
+                if (pass == 0 ? d <= 1 : d == 2) {
+                    sel.push_back(v);
+                    mark(v);
+                }
+            }
+        for (int32_t k : sel) {
+            Elim e{k, -1, -1, false};
+            const int32_t par = cp[k];
+            const int32_t c1 = fc[k], c2 = c1 >= 0 ? ns[c1] : -1;
+            if (par >= 0) {
+                e.n1 = par;
+                e.n1_parent = true;
+                e.n2 = c1;  // at most one child
+                unlink(k);
+                if (c1 >= 0) {
+                    unlink(c1);
+                    link(c1, par);
+                }
+            } else if (c1 >= 0) {
+                if (c2 >= 0) {  // a root with two children: c2 hangs off c1
+                    e.n1 = c1;
+                    e.n2 = c2;
+                    unlink(c1);
+                    unlink(c2);
+                    link(c2, c1);
+                } else {  // a root with one child: the child becomes the root
+                    e.n2 = c1;
+                    unlink(c1);
+                }
+            }
+            items.push_back(e);
+            stamp[k] = -1;  // eliminated
+        }
+        next.clear();
+        for (int32_t v : alive)
+            if (stamp[v] != -1) next.push_back(v);
+        alive.swap(next);
+        round_off.push_back((int32_t)items.size());
+    }
+}
+
 void features(const NeuronTopo &t, const uint8_t *mech, int32_t nsyn, int32_t nseg,
               float *f) {
     const int32_t nb = (int32_t)t.b0.size();
@@ -157,6 +262,7 @@ void features(const NeuronTopo &t, const uint8_t *mech, int32_t nsyn, int32_t ns
 // Launch variant and device buffers.
 // ---------------------------------------------------------------------------
 constexpr int kClasses = 3;
+constexpr int64_t kRingMin = 32;  // spike ring rows (epochs) at least
 
 // One launch of the epoch kernel over the packs of one size class: its
 // workgroup count, dynamic LDS, and where its lists start in the shared
@@ -224,8 +330,23 @@ struct sim {
     std::vector<int64_t> syn_by_post;  // synapse ids grouped by post, ascending id
     std::vector<int64_t> syn_post_off; // [N+1]
     std::vector<double> cost;          // packing cost per neuron
+    // contraction solver: per neuron, its items (neuron-local, in round
+    // order, at the neuron's compartment offsets) and round offsets
+    std::vector<uint64_t> citems;
+    std::vector<int32_t> croff;
+    std::vector<int64_t> croff0;       // [N+1] into croff
 
-    // layout
+    // layout: the host arrays build_layout produces, held until uploaded
+    struct HostLayout {
+        std::vector<uint32_t> topo;
+        std::vector<int32_t> lparent, nid, ndet, lvl, spre, sdel;
+        std::vector<double> len, dia, w64, iext64;
+        std::vector<int64_t> ncomp0;
+        std::vector<uint16_t> scomp, sseg, chl, fws;
+        std::vector<Branch> brs;
+        std::vector<uint64_t> cit;
+    } hl;
+    bool planned_only = false;  // laid out on the host, no device (sim_plan_create)
     Variant var;
     std::vector<int32_t> order;        // packed position -> input neuron
     std::vector<int64_t> comp_perm;    // packed compartment -> input compartment
@@ -254,10 +375,27 @@ struct sim {
     DBuf<uint16_t> d_scomp, d_sseg, d_chl;
     DBuf<Branch> d_br;
     DBuf<uint16_t> d_fw;
+    DBuf<uint64_t> d_cit;
     DBuf<int64_t> d_ncomp0, d_epoch;
-    DBuf<uint64_t> d_hist, d_ptime;
-    int64_t hist_epochs = 0;
+    DBuf<uint64_t> d_ring, d_ptime;
     double q = 0;
+
+    // spike history: a device ring of ring_rows epoch rows (enough for the
+    // longest delay), drained after every stretch of at most ring_rows epochs
+    // into pinned staging (two slots, so the host reads one while the device
+    // fills the other) and from there into the host spike list
+    int32_t ring_rows = 0;
+    uint64_t *h_stage[2] = {nullptr, nullptr};
+    hipEvent_t ev_stage[2] = {};
+    struct Drain {
+        int64_t first_epoch = 0;
+        int32_t rows = 0;
+        int64_t lo = 0, hi = 0;  // spikes of steps (lo, hi]
+        bool pending = false;
+    } drain[2];
+    int drain_slot = 0;
+    std::vector<sim_spike_t> spikes;      // sorted by (step, neuron)
+    std::vector<std::vector<int32_t>> by_t;  // scan scratch, one list per epoch step
 
     // time
     int64_t step = 0;
@@ -278,6 +416,7 @@ struct sim {
     double kt_cls_ms[kClasses] = {};
     int64_t kt_cls_n[kClasses] = {};
     int64_t cls_comps[kClasses] = {};  // compartments of each size class
+    int64_t kt_cls_upd[kClasses] = {};  // compartment-updates launched while timing is on
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double tick_ns = 10.0;
 
@@ -304,7 +443,8 @@ void validate(const sim_params_t *P, const sim_morphology_t *M, const sim_channe
         throw fail(SIM_EINVAL, "cm and ra must be > 0");
     if (P->precision != SIM_FP64 && P->precision != SIM_FP32_GATING)
         throw fail(SIM_EINVAL, "unknown precision %d", P->precision);
-    if (P->solver != SIM_SOLVE_EXACT && P->solver != SIM_SOLVE_FAST)
+    if (P->solver != SIM_SOLVE_EXACT && P->solver != SIM_SOLVE_FAST &&
+        P->solver != SIM_SOLVE_CONTRACT)
         throw fail(SIM_EINVAL, "unknown solver %d", P->solver);
     if (P->packing < SIM_PACK_PLAIN || P->packing > SIM_PACK_LEARNED)
         throw fail(SIM_EINVAL, "unknown packing %d", P->packing);
@@ -397,6 +537,17 @@ void copy_inputs(sim_t *s, const sim_params_t *P, const sim_morphology_t *M,
     int64_t mind = 64;
     for (int64_t k = 0; k < s->S; ++k) mind = std::min<int64_t>(mind, s->delay[k]);
     s->E = P->epoch_steps > 0 ? P->epoch_steps : (int)mind;
+    // ring rows: delivery in epoch k reads epochs k - ceil((delay + 1) / E)
+    // .. k - 1 while epoch k writes its own row, so that many + 1 rows must be
+    // distinct; at least kRingMin so that draining stays rare
+    int64_t maxd = 0;
+    for (int64_t k = 0; k < s->S; ++k) maxd = std::max<int64_t>(maxd, s->delay[k]);
+    const int64_t need = (maxd + 1 + s->E - 1) / s->E + 1;
+    const int64_t rows = std::max<int64_t>(need, kRingMin);
+    if (rows * (int64_t)s->N * 8 > (int64_t)16 << 30)
+        throw fail(SIM_ENOMEM, "spike ring of %lld epochs x %d neurons exceeds 16 GiB (longest delay "
+                   "%lld steps)", (long long)rows, s->N, (long long)maxd);
+    s->ring_rows = (int32_t)rows;
 }
 
 void analyse_all(sim_t *s) {
@@ -425,6 +576,31 @@ void analyse_all(sim_t *s) {
         const int32_t nseg = (int32_t)(std::unique(seen.begin(), seen.end()) - seen.begin());
         features(s->topo[j], s->mech.data() + b, s->nsyn_of[j], nseg, &s->feat[(size_t)j * kFeat]);
     }
+    s->citems.clear();
+    s->croff.clear();
+    s->croff0.assign(1, 0);
+    if (s->solver == SIM_SOLVE_CONTRACT) {
+        s->citems.resize(s->C);
+        std::vector<Elim> items;
+        std::vector<int32_t> roff;
+        for (int32_t j = 0; j < s->N; ++j) {
+            const int64_t b = s->off[j];
+            const int32_t n = (int32_t)(s->off[j + 1] - b);
+            contraction_schedule(s->parent.data() + b, n, items, roff);
+            for (int32_t q = 0; q < n; ++q) {
+                const Elim &e = items[q];
+                s->citems[b + q] = make_item((uint32_t)e.k, e.n1_parent,
+                                             e.n1 < 0 ? kNoNb : (uint32_t)e.n1,
+                                             e.n2 < 0 ? kNoNb : (uint32_t)e.n2);
+            }
+            s->croff.insert(s->croff.end(), roff.begin(), roff.end());
+            s->croff0.push_back((int64_t)s->croff.size());
+        }
+    }
+}
+
+int32_t contraction_rounds(const sim_t *s, int32_t j) {
+    return s->croff0.size() > (size_t)j + 1 ? (int32_t)(s->croff0[j + 1] - s->croff0[j] - 1) : 0;
 }
 
 void compute_cost(sim_t *s) {
@@ -510,27 +686,29 @@ void build_layout(sim_t *s, Variant v) {
         struct Bin {
             std::vector<int32_t> members;
             int64_t n = 0, ns = 0;
-            int32_t nbr = 0, nch = 0, maxh = 0, maxd = 0;
+            int32_t nbr = 0, nch = 0, maxh = 0, maxd = 0, maxr = 0;
             int cls = 0;
             double cost = 0.0;
         };
         auto bytes_of = [&](int64_t n, int64_t ns, int32_t nbr, int32_t nch, int32_t maxh,
-                            int32_t maxd, int64_t k) -> int64_t {
+                            int32_t maxd, int32_t maxr, int64_t k) -> int64_t {
             const int64_t nlev = (int64_t)maxh + maxd + 4;
-            return s->tsize == 8
-                       ? pack_table_bytes<double>(nbr, nch, nlev, ns) + pack_state_bytes<double>(n, ns, k)
-                       : pack_table_bytes<float>(nbr, nch, nlev, ns) + pack_state_bytes<float>(n, ns, k);
+            return s->tsize == 8 ? pack_table_bytes<double>(nbr, nch, nlev, ns, n, maxr) +
+                                       pack_state_bytes<double>(n, ns, k)
+                                 : pack_table_bytes<float>(nbr, nch, nlev, ns, n, maxr) +
+                                       pack_state_bytes<float>(n, ns, k);
         };
         std::vector<Bin> bins;
         std::multimap<int64_t, int32_t> open;  // LDS bytes left -> bin
         std::vector<std::multimap<int64_t, int32_t>::iterator> where;
-        const int64_t base_bytes = bytes_of(0, 0, 0, 0, 0, 0, 0);
+        const int64_t base_bytes = bytes_of(0, 0, 0, 0, 0, 0, 0, 0);
         for (int32_t q = 0; q < N; ++q) {
             const int32_t j = s->order[q];
             const NeuronTopo &t = s->topo[j];
             const int64_t n = s->off[j + 1] - s->off[j], ns = s->nsyn_of[j];
             const int32_t nb = (int32_t)t.b0.size();
-            const int64_t alone = bytes_of(n, ns, nb, nb - 1, t.max_height, t.max_depth, 1);
+            const int32_t nr = contraction_rounds(s, j);
+            const int64_t alone = bytes_of(n, ns, nb, nb - 1, t.max_height, t.max_depth, nr, 1);
             int32_t chosen = -1;
             int tries = 0;
             for (auto it = open.lower_bound(alone - base_bytes); it != open.end() && tries < 32;
@@ -541,7 +719,7 @@ void build_layout(sim_t *s, Variant v) {
                     continue;
                 const int64_t with = bytes_of(B.n + n, B.ns + ns, B.nbr + nb, B.nch + nb - 1,
                                               std::max(B.maxh, t.max_height),
-                                              std::max(B.maxd, t.max_depth),
+                                              std::max(B.maxd, t.max_depth), std::max(B.maxr, nr),
                                               (int64_t)B.members.size() + 1);
                 if (with <= cls_budget[B.cls]) {
                     chosen = it->second;
@@ -566,8 +744,9 @@ void build_layout(sim_t *s, Variant v) {
             B.nch += nb - 1;
             B.maxh = std::max(B.maxh, t.max_height);
             B.maxd = std::max(B.maxd, t.max_depth);
+            B.maxr = std::max(B.maxr, nr);
             B.cost = learned ? std::max(B.cost, s->cost[j]) : B.cost + s->cost[j];
-            const int64_t used = bytes_of(B.n, B.ns, B.nbr, B.nch, B.maxh, B.maxd,
+            const int64_t used = bytes_of(B.n, B.ns, B.nbr, B.nch, B.maxh, B.maxd, B.maxr,
                                           (int64_t)B.members.size());
             if (used <= cls_budget[B.cls])  // (a pack too large for LDS stays alone)
                 where[chosen] = open.emplace(cls_budget[B.cls] - used, chosen);
@@ -594,14 +773,17 @@ void build_layout(sim_t *s, Variant v) {
     s->pack_cost.assign(npk, 0.0);
     s->pack_of_neuron.assign(N, 0);
 
-    std::vector<uint32_t> topo;
-    std::vector<int32_t> lparent, nid, ndet, lvl;
-    std::vector<double> len, dia, w64, iext64;
-    std::vector<int64_t> ncomp0;
-    std::vector<int32_t> spre, sdel;
-    std::vector<uint16_t> scomp, sseg, chl;
-    std::vector<Branch> brs;
-    std::vector<uint16_t> fws;  // forward order: record ids
+    s->hl = sim_t::HostLayout{};
+    auto &topo = s->hl.topo;
+    auto &lparent = s->hl.lparent, &nid = s->hl.nid, &ndet = s->hl.ndet, &lvl = s->hl.lvl;
+    auto &len = s->hl.len, &dia = s->hl.dia, &w64 = s->hl.w64, &iext64 = s->hl.iext64;
+    auto &ncomp0 = s->hl.ncomp0;
+    auto &spre = s->hl.spre, &sdel = s->hl.sdel;
+    auto &scomp = s->hl.scomp, &sseg = s->hl.sseg, &chl = s->hl.chl;
+    auto &brs = s->hl.brs;
+    auto &fws = s->hl.fws;  // forward order: record ids
+    auto &cit = s->hl.cit;  // contraction items, pack-local, by pack and round
+    std::vector<int32_t> member_base;  // compartment base of each neuron in the pack
     // per-pack branch scratch (pack-local branch index = br_base + local)
     std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0;
     topo.reserve(s->C);
@@ -631,6 +813,7 @@ void build_layout(sim_t *s, Variant v) {
         d.nbr = pk[p].nbr;
         d.ch0 = (int32_t)chl.size();
         d.lv0 = (int32_t)lvl.size();
+        member_base.clear();
         tb0.clear();
         tb1.clear();
         tpar.clear();
@@ -683,6 +866,7 @@ void build_layout(sim_t *s, Variant v) {
                 const int64_t sid = s->syn_by_post[qq];
                 segs.emplace_back((int64_t)comp_base + s->pcomp[sid], sid);
             }
+            member_base.push_back(comp_base);
             comp_base += n;
             br_base += nb;
         }
@@ -776,9 +960,44 @@ void build_layout(sim_t *s, Variant v) {
             lvl.push_back((int32_t)(fws.size() - d.br0));
         }
         d.nch = (int32_t)chl.size() - d.ch0;
+        d.it0 = 0;
+        d.nrnd = 0;
+        if (s->solver == SIM_SOLVE_CONTRACT) {
+            // round r of the pack: round r of each of its neurons, in pack
+            // order, renumbered pack-locally; offsets follow the levels
+            d.it0 = (int32_t)cit.size();
+            int32_t maxr = 0;
+            for (int32_t k = 0; k < pk[p].count; ++k)
+                maxr = std::max(maxr, contraction_rounds(s, s->order[pk[p].first + k]));
+            d.nrnd = maxr;
+            lvl.push_back(0);
+            for (int32_t r = 0; r < maxr; ++r) {
+                for (int32_t k = 0; k < pk[p].count; ++k) {
+                    const int32_t j = s->order[pk[p].first + k];
+                    if (r >= contraction_rounds(s, j)) continue;
+                    const int32_t *ro = s->croff.data() + s->croff0[j];
+                    const uint32_t base = (uint32_t)member_base[k];
+                    for (int32_t q = ro[r]; q < ro[r + 1]; ++q) {
+                        const uint64_t it = s->citems[s->off[j] + q];
+                        const uint32_t kk = (uint32_t)(it & 0x7FFFu);
+                        const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu;
+                        const uint32_t n2 = (uint32_t)(it >> 32) & 0xFFFFu;
+                        cit.push_back(make_item(base + kk, (it >> 15) & 1u,
+                                                n1 == kNoNb ? kNoNb : base + n1,
+                                                n2 == kNoNb ? kNoNb : base + n2));
+                    }
+                }
+                lvl.push_back((int32_t)(cit.size() - d.it0));
+            }
+            if ((int64_t)cit.size() - d.it0 != d.ncomp)
+                throw fail(SIM_EINVAL, "internal: contraction schedule does not cover the pack");
+            if (cit.size() > (size_t)INT32_MAX) throw fail(SIM_ENOMEM, "contraction table too large");
+        }
         d.tbytes = (int32_t)(s->tsize == 8
-                                 ? pack_table_bytes<double>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn)
-                                 : pack_table_bytes<float>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn));
+                                 ? pack_table_bytes<double>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn,
+                                                            d.ncomp, d.nrnd)
+                                 : pack_table_bytes<float>(d.nbr, d.nch, d.nbw + d.nfw + 2, d.nsyn,
+                                                           d.ncomp, d.nrnd));
         // size class: 0 = fits the small LDS budget (many workgroups per CU),
         // 1 = needs a larger LDS allocation (its own concurrent launch), or
         // does not fit LDS at all (state in global scratch, same launch)
@@ -861,28 +1080,34 @@ void build_layout(sim_t *s, Variant v) {
     s->n_wg = 0;
     for (int c = 0; c < kClasses; ++c) s->n_wg += s->launch[c].n_wg;
     s->lds_bytes = s->launch[0].lds;
+}
 
-    // device upload
+// Device copy of the layout build_layout left in s->hl, and the state arrays.
+void upload_layout(sim_t *s) {
+    sim_t::HostLayout &h = s->hl;
+    const int32_t N = s->N;
+    const int npk = (int)s->packs.size();
     s->d_packs.upload(s->packs);
     s->d_wg_off.upload(s->wg_off);
     s->d_wg_list.upload(s->wg_list);
-    s->d_topo.upload(topo);
-    s->d_lparent.upload(lparent);
-    s->d_len.upload(len);
-    s->d_diam.upload(dia);
-    s->d_ncomp0.upload(ncomp0);
-    s->d_nid.upload(nid);
-    s->d_ndet.upload(ndet);
-    s->d_iext64.upload(iext64);
-    s->d_spre.upload(spre);
-    s->d_sdelay.upload(sdel);
-    s->d_w64.upload(w64);
-    s->d_scomp.upload(scomp);
-    s->d_sseg.upload(sseg);
-    s->d_br.upload(brs);
-    s->d_fw.upload(fws);
-    s->d_chl.upload(chl);
-    s->d_lvl.upload(lvl);
+    s->d_topo.upload(h.topo);
+    s->d_lparent.upload(h.lparent);
+    s->d_len.upload(h.len);
+    s->d_diam.upload(h.dia);
+    s->d_ncomp0.upload(h.ncomp0);
+    s->d_nid.upload(h.nid);
+    s->d_ndet.upload(h.ndet);
+    s->d_iext64.upload(h.iext64);
+    s->d_spre.upload(h.spre);
+    s->d_sdelay.upload(h.sdel);
+    s->d_w64.upload(h.w64);
+    s->d_scomp.upload(h.scomp);
+    s->d_sseg.upload(h.sseg);
+    s->d_br.upload(h.brs);
+    s->d_fw.upload(h.fws);
+    s->d_cit.upload(h.cit);
+    s->d_chl.upload(h.chl);
+    s->d_lvl.upload(h.lvl);
     const int64_t C = s->C, S = s->S;
     s->d_V.alloc(C);
     s->d_cdt.alloc(C);
@@ -898,6 +1123,7 @@ void build_layout(sim_t *s, Variant v) {
     s->d_scratch.alloc(256);
     s->d_ptime.alloc(npk);
     HIPCHK(hipMemset(s->d_ptime.p, 0, sizeof(uint64_t) * npk));
+    s->hl = sim_t::HostLayout{};  // the device holds it now
 }
 
 void init_state(sim_t *s) {
@@ -929,8 +1155,11 @@ void init_state(sim_t *s) {
     HIPCHK(hipStreamSynchronize(s->stream));
     HIPCHK(hipMemcpy(&s->q, s->d_q.p, sizeof(double), hipMemcpyDeviceToHost));
     s->step = 0;
-    if (s->d_hist.p && s->d_hist.n) HIPCHK(launch_fill_u64(s->d_hist.p, s->d_hist.n, 0, s->stream));
+    if (s->d_ring.p && s->d_ring.n) HIPCHK(launch_fill_u64(s->d_ring.p, s->d_ring.n, 0, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    s->spikes.clear();
+    s->drain[0].pending = s->drain[1].pending = false;
+    s->drain_slot = 0;
 }
 
 void destroy_graphs(sim_t *s) {
@@ -940,22 +1169,6 @@ void destroy_graphs(sim_t *s) {
     if (s->graphK) (void)hipGraphDestroy(s->graphK);
     s->exec1 = s->execK = nullptr;
     s->graph1 = s->graphK = nullptr;
-}
-
-void ensure_hist(sim_t *s, int64_t epochs_needed) {
-    if (epochs_needed <= s->hist_epochs) return;
-    int64_t cap = std::max<int64_t>(epochs_needed, std::max<int64_t>(16, s->hist_epochs * 2));
-    DBuf<uint64_t> nb;
-    nb.alloc(cap * s->N);
-    HIPCHK(launch_fill_u64(nb.p, nb.n, 0, s->stream));
-    if (s->d_hist.p && s->hist_epochs)
-        HIPCHK(hipMemcpyAsync(nb.p, s->d_hist.p, sizeof(uint64_t) * s->hist_epochs * s->N,
-                              hipMemcpyDeviceToDevice, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    s->d_hist.free_();
-    s->d_hist = nb;
-    s->hist_epochs = cap;
-    destroy_graphs(s);
 }
 
 EpochArgs make_args(sim_t *s) {
@@ -984,7 +1197,9 @@ EpochArgs make_args(sim_t *s) {
     a.fw = s->d_fw.p;
     a.chl = s->d_chl.p;
     a.lvl = s->d_lvl.p;
-    a.hist = s->d_hist.p;
+    a.cit = s->d_cit.p;
+    a.ring = s->d_ring.p;
+    a.ring_rows = s->ring_rows;
     a.n_neurons = s->N;
     a.E = s->E;
     a.scratch = s->d_scratch.p;
@@ -1129,10 +1344,76 @@ void capture(sim_t *s, int epochs, hipGraph_t &g, hipGraphExec_t &ex) {
     HIPCHK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
 }
 
+// Spikes of the steps (lo, hi] staged in `slot`, appended to the host list in
+// (step, neuron) order once the copy has landed.
+void scan_stage(sim_t *s, int slot) {
+    sim_t::Drain &d = s->drain[slot];
+    if (!d.pending) return;
+    HIPCHK(hipEventSynchronize(s->ev_stage[slot]));
+    const int E = s->E;
+    s->by_t.resize(E);
+    for (int32_t r = 0; r < d.rows; ++r) {
+        const int64_t e = d.first_epoch + r;
+        for (auto &v : s->by_t) v.clear();
+        const uint64_t *w = s->h_stage[slot] + (size_t)r * s->N;
+        for (int32_t j = 0; j < s->N; ++j)
+            for (uint64_t m = w[j]; m; m &= m - 1) s->by_t[__builtin_ctzll(m)].push_back(j);
+        for (int t = 0; t < E; ++t) {
+            const int64_t step = e * E + t + 1;
+            if (step <= d.lo || step > d.hi) continue;
+            for (int32_t j : s->by_t[t]) s->spikes.push_back(sim_spike_t{j, (int32_t)step});
+        }
+    }
+    d.pending = false;
+}
+
+// After the steps (lo, hi] are enqueued: copy their ring rows to the next
+// staging slot behind them on the stream (the slot's previous contents are
+// read first).
+void enqueue_drain(sim_t *s, int64_t lo, int64_t hi) {
+    if (hi <= lo) return;
+    const int E = s->E, R = s->ring_rows;
+    const int64_t e0 = lo / E, e1 = (hi - 1) / E;
+    const int slot = s->drain_slot;
+    scan_stage(s, slot);
+    const int32_t rows = (int32_t)(e1 - e0 + 1);
+    if (rows > R) throw fail(SIM_ESTATE, "drain of %d epochs exceeds the ring", rows);
+    for (int32_t r = 0; r < rows;) {
+        const int64_t row = (e0 + r) % R;
+        const int32_t n = (int32_t)std::min<int64_t>(rows - r, R - row);
+        HIPCHK(hipMemcpyAsync(s->h_stage[slot] + (size_t)r * s->N, s->d_ring.p + row * s->N,
+                              sizeof(uint64_t) * (size_t)n * s->N, hipMemcpyDeviceToHost,
+                              s->stream));
+        r += n;
+    }
+    HIPCHK(hipEventRecord(s->ev_stage[slot], s->stream));
+    s->drain[slot] = sim_t::Drain{e0, rows, lo, hi, true};
+    s->drain_slot = slot ^ 1;
+}
+
+void advance(sim_t *s, int64_t n);
+
+// Steps in stretches that never overwrite a ring row before it is staged: a
+// stretch ends before the epoch ring_rows after its first one begins.
 void run_steps(sim_t *s, int64_t n) {
     if (n <= 0) return;
     const int E = s->E;
-    ensure_hist(s, (s->step + n + E - 1) / E + 1);
+    while (n > 0) {
+        const int64_t lo = s->step;
+        const int64_t room = (lo / E + s->ring_rows) * E - lo;
+        const int64_t m = std::min(n, room);
+        advance(s, m);
+        enqueue_drain(s, lo, s->step);
+        n -= m;
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    scan_stage(s, s->drain_slot);  // older first
+    scan_stage(s, s->drain_slot ^ 1);
+    if (s->kt_on) kt_collect(s);
+}
+
+void advance(sim_t *s, int64_t n) {
+    const int E = s->E;
     while (n > 0) {
         const int64_t ep = s->step / E;
         const int t0 = (int)(s->step % E);
@@ -1159,6 +1440,9 @@ void run_steps(sim_t *s, int64_t n) {
                 replay(s->exec1, 1);
                 left -= 1;
             }
+            if (s->kt_on)
+                for (int c = 0; c < kClasses; ++c)
+                    if (s->launch[c].n_wg > 0) s->kt_cls_upd[c] += s->cls_comps[c] * full * E;
             s->step += full * E;
             n -= full * E;
             continue;
@@ -1170,12 +1454,14 @@ void run_steps(sim_t *s, int64_t n) {
             HIPCHK(hipEventRecord(ev.first, s->stream));
         }
         launch_range(s, ep, t0, t1, false);
-        if (s->kt_on) HIPCHK(hipEventRecord(ev.second, s->stream));
+        if (s->kt_on) {
+            HIPCHK(hipEventRecord(ev.second, s->stream));
+            for (int c = 0; c < kClasses; ++c)
+                if (s->launch[c].n_wg > 0) s->kt_cls_upd[c] += s->cls_comps[c] * (t1 - t0);
+        }
         s->step += t1 - t0;
         n -= t1 - t0;
     }
-    HIPCHK(hipStreamSynchronize(s->stream));
-    if (s->kt_on) kt_collect(s);
 }
 
 std::string describe(const sim_t *s) {
@@ -1193,7 +1479,8 @@ std::string describe(const sim_t *s) {
              s->launch[0].threads, s->launch[1].threads, s->launch[2].threads,
              s->launch[0].lds, s->launch[1].lds, s->launch[2].lds, s->E,
              s->precision == SIM_FP64 ? "fp64" : "fp32-gating",
-             s->solver == SIM_SOLVE_FAST ? "fast" : "exact",
+             s->solver == SIM_SOLVE_FAST ? "fast"
+             : s->solver == SIM_SOLVE_CONTRACT ? "contract" : "exact",
              s->P.packing == SIM_PACK_PLAIN ? "plain"
              : s->P.packing == SIM_PACK_COUNT ? "count"
              : s->cost_model.empty() ? "learned(fallback count)" : "learned");
@@ -1203,6 +1490,7 @@ std::string describe(const sim_t *s) {
 void apply_variant(sim_t *s, const Variant &v) {
     destroy_graphs(s);
     build_layout(s, v);
+    upload_layout(s);
     assign_scratch(s);
     init_state(s);
     s->config = describe(s);
@@ -1247,7 +1535,6 @@ void autotune(sim_t *s, Variant base) {
     Variant bestv = base;
     for (const Variant &v : cand) {
         apply_variant(s, v);
-        ensure_hist(s, 2);
         launch_range(s, 0, 0, s->E, false);  // warm-up
         HIPCHK(hipStreamSynchronize(s->stream));
         HIPCHK(hipEventRecord(s->ev0, s->stream));
@@ -1262,6 +1549,18 @@ void autotune(sim_t *s, Variant base) {
         }
     }
     apply_variant(s, bestv);
+}
+
+// The launch variant the parameters ask for (before autotuning).
+Variant variant_from(const sim_t *s, const sim_params_t *params) {
+    Variant v;
+    v.threads = params->threads ? params->threads : 256;
+    v.pack_comps = params->pack_comps ? params->pack_comps : 800;
+    v.comp_cap = params->pack_comps;
+    v.lds_limit = lds_for(s, params->lds_comps ? params->lds_comps : 1100);
+    if (params->lds_classes) v.nclass = params->lds_classes;
+    v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
+    return v;
 }
 
 }  // namespace
@@ -1337,14 +1636,14 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
         s->d_epoch.alloc(1);
         s->d_ktimer.alloc(8 * kClasses);
         ktimer_reset(s);
+        s->d_ring.alloc((int64_t)s->ring_rows * s->N);
+        for (int k = 0; k < 2; ++k) {
+            HIPCHK(hipHostMalloc((void **)&s->h_stage[k],
+                                 sizeof(uint64_t) * (size_t)s->ring_rows * s->N, hipHostMallocDefault));
+            HIPCHK(hipEventCreateWithFlags(&s->ev_stage[k], hipEventDisableTiming));
+        }
         compute_cost(s);
-        Variant v;
-        v.threads = params->threads ? params->threads : 256;
-        v.pack_comps = params->pack_comps ? params->pack_comps : 800;
-        v.comp_cap = params->pack_comps;
-        v.lds_limit = lds_for(s, params->lds_comps ? params->lds_comps : 1100);
-        if (params->lds_classes) v.nclass = params->lds_classes;
-        v.sched = params->sched == SIM_SCHED_PERSISTENT ? SIM_SCHED_PERSISTENT : SIM_SCHED_DISPATCH;
+        const Variant v = variant_from(s, params);
         if (params->autotune)
             autotune(s, v);
         else
@@ -1362,8 +1661,134 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
     }
 }
 
+int sim_plan_create(const sim_params_t *params, const sim_morphology_t *morph,
+                    const sim_channels_t *channels, const sim_synapses_t *syn,
+                    int32_t lds_bytes_per_cu, int32_t n_cu, sim_t **out) {
+    if (!out) {
+        g_create_error = "null output pointer";
+        return SIM_EINVAL;
+    }
+    *out = nullptr;
+    sim_t *s = nullptr;
+    try {
+        validate(params, morph, channels, syn);
+        if (lds_bytes_per_cu < 4096 || lds_bytes_per_cu > (1 << 20) || n_cu < 1)
+            throw fail(SIM_EINVAL, "plan needs 4096 <= lds_bytes_per_cu <= 1 MiB and n_cu >= 1");
+        if (params->packing == SIM_PACK_LEARNED && params->cost_model)
+            throw fail(SIM_EINVAL, "a learned cost model needs the device (sim_create)");
+        if (params->autotune) throw fail(SIM_EINVAL, "autotuning needs the device (sim_create)");
+        s = new sim_t();
+        s->planned_only = true;
+        copy_inputs(s, params, morph, channels, syn);
+        analyse_all(s);
+        s->max_lds = lds_bytes_per_cu;
+        s->n_cu = n_cu;
+        compute_cost(s);
+        build_layout(s, variant_from(s, params));
+        s->hl = sim_t::HostLayout{};
+        s->config = describe(s);
+        *out = s;
+        return SIM_OK;
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        if (s) sim_destroy(s);
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_create_error = "host allocation failed";
+        if (s) sim_destroy(s);
+        return SIM_ENOMEM;
+    }
+}
+
+int32_t sim_pack_count(const sim_t *s) { return s ? (int32_t)s->packs.size() : -1; }
+
+int sim_pack_info(const sim_t *s, int32_t pack, sim_pack_info_t *out) {
+    if (!s || !out || pack < 0 || pack >= (int32_t)s->packs.size()) return SIM_EINVAL;
+    const PackDesc &d = s->packs[pack];
+    int cls = -1;
+    for (int c = 0; c < kClasses && cls < 0; ++c) {
+        const Launch &L = s->launch[c];
+        for (int32_t w = 0; w < L.n_wg && cls < 0; ++w)
+            for (int32_t q = s->wg_off[L.off0 + w]; q < s->wg_off[L.off0 + w + 1]; ++q)
+                if (s->wg_list[L.list0 + q] == pack) {
+                    cls = c;
+                    break;
+                }
+    }
+    out->first_position = d.neur0;
+    out->n_neurons = d.nneur;
+    out->n_comp = d.ncomp;
+    out->n_syn = d.nsyn;
+    out->n_branches = d.nbr;
+    out->size_class = cls;
+    out->in_global = d.global_mem ? 1 : 0;
+    out->n_rounds = d.nrnd;
+    out->n_levels = d.nbw + d.nfw + 2;
+    out->n_child_entries = d.nch;
+    out->table_bytes = d.tbytes;
+    out->state_bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
+    out->cost = s->pack_cost[pack];
+    return SIM_OK;
+}
+
+int sim_pack_neurons(const sim_t *s, int32_t pack, int32_t *ids, int64_t cap) {
+    if (!s || !ids || pack < 0 || pack >= (int32_t)s->packs.size()) return SIM_EINVAL;
+    const PackDesc &d = s->packs[pack];
+    if (cap < d.nneur) return SIM_EINVAL;
+    for (int32_t k = 0; k < d.nneur; ++k) ids[k] = s->order[d.neur0 + k];
+    return SIM_OK;
+}
+
+int sim_class_launch(const sim_t *s, int32_t cls, int32_t *n_wg, int32_t *threads,
+                     int64_t *lds_bytes) {
+    if (!s || cls < 0 || cls >= kClasses) return SIM_EINVAL;
+    if (n_wg) *n_wg = s->launch[cls].n_wg;
+    if (threads) *threads = s->launch[cls].threads;
+    if (lds_bytes) *lds_bytes = (int64_t)s->launch[cls].lds;
+    return SIM_OK;
+}
+
+int sim_workgroup_packs(const sim_t *s, int32_t cls, int32_t wg, int32_t *packs, int64_t cap,
+                        int32_t *n) {
+    if (!s || cls < 0 || cls >= kClasses) return SIM_EINVAL;
+    const Launch &L = s->launch[cls];
+    if (wg < 0 || wg >= L.n_wg) return SIM_EINVAL;
+    const int32_t q0 = s->wg_off[L.off0 + wg], q1 = s->wg_off[L.off0 + wg + 1];
+    if (n) *n = q1 - q0;
+    if (!packs) return SIM_OK;
+    if (cap < q1 - q0) return SIM_EINVAL;
+    for (int32_t q = q0; q < q1; ++q) packs[q - q0] = s->wg_list[L.list0 + q];
+    return SIM_OK;
+}
+
+int sim_contraction_schedule(const sim_t *s, int32_t neuron, int32_t *items, int64_t cap,
+                             int32_t *round_off, int64_t cap_rounds, int32_t *n_rounds) {
+    if (!s || neuron < 0 || neuron >= s->N) return SIM_EINVAL;
+    if (s->solver != SIM_SOLVE_CONTRACT) return SIM_ESTATE;
+    const int32_t nr = contraction_rounds(s, neuron);
+    const int64_t n = s->off[neuron + 1] - s->off[neuron];
+    if (n_rounds) *n_rounds = nr;
+    if (!items) return SIM_OK;
+    if (cap < 4 * n || !round_off || cap_rounds < nr + 1) return SIM_EINVAL;
+    for (int64_t q = 0; q < n; ++q) {
+        const uint64_t it = s->citems[s->off[neuron] + q];
+        const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
+        items[4 * q + 0] = (int32_t)(it & 0x7FFFu);
+        items[4 * q + 1] = n1 == kNoNb ? -1 : (int32_t)n1;
+        items[4 * q + 2] = n2 == kNoNb ? -1 : (int32_t)n2;
+        items[4 * q + 3] = (int32_t)((it >> 15) & 1u);
+    }
+    const int32_t *ro = s->croff.data() + s->croff0[neuron];
+    for (int32_t r = 0; r <= nr; ++r) round_off[r] = ro[r];
+    return SIM_OK;
+}
+
 int sim_step(sim_t *s, int64_t n_steps) {
     if (!s) return SIM_EINVAL;
+    if (s->planned_only) {
+        s->err = "a planned simulation has no device state";
+        return SIM_ESTATE;
+    }
     if (n_steps < 0) {
         s->err = "n_steps must be >= 0";
         return SIM_EINVAL;
@@ -1379,8 +1804,16 @@ int sim_step(sim_t *s, int64_t n_steps) {
 
 int64_t sim_time_steps(const sim_t *s) { return s ? s->step : -1; }
 
+// Calls that need device state refuse a simulation that was only planned.
+static bool need_device(sim_t *s) {
+    if (!s->planned_only) return true;
+    s->err = "a planned simulation has no device state";
+    return false;
+}
+
 static int read_comp(sim_t *s, const char *src, int64_t cap, int elem, double *out) {
     if (!s || !out) return SIM_EINVAL;
+    if (!need_device(s)) return SIM_ESTATE;
     if (cap < s->C) {
         s->err = "capacity smaller than the compartment count";
         return SIM_EINVAL;
@@ -1420,6 +1853,7 @@ int sim_read_gates(sim_t *s, double *m, double *h, double *n, int64_t cap) {
 
 int sim_read_conductances(sim_t *s, double *out, int64_t cap) {
     if (!s || !out) return SIM_EINVAL;
+    if (!need_device(s)) return SIM_ESTATE;
     if (cap < s->S) {
         s->err = "capacity smaller than the synapse count";
         return SIM_EINVAL;
@@ -1447,36 +1881,20 @@ int sim_read_conductances(sim_t *s, double *out, int64_t cap) {
 
 int sim_spikes(sim_t *s, sim_spike_t *out, int64_t cap, int64_t *n_total) {
     if (!s) return SIM_EINVAL;
-    try {
-        const int64_t ne = (s->step + s->E - 1) / s->E;
-        std::vector<uint64_t> h((size_t)ne * s->N);
-        if (ne) HIPCHK(hipMemcpy(h.data(), s->d_hist.p, sizeof(uint64_t) * h.size(), hipMemcpyDeviceToHost));
-        int64_t total = 0;
-        for (uint64_t w : h) total += __builtin_popcountll(w);
-        if (n_total) *n_total = total;
-        if (!out) return SIM_OK;  // count query
-        if (cap < total) {
-            s->err = "spike buffer too small";
-            return SIM_EINVAL;
-        }
-        int64_t k = 0;
-        for (int64_t e = 0; e < ne; ++e)
-            for (int t = 0; t < s->E; ++t)
-                for (int32_t j = 0; j < s->N; ++j)
-                    if ((h[(size_t)e * s->N + j] >> t) & 1ull) {
-                        out[k].neuron = j;
-                        out[k].step = (int32_t)(e * s->E + t + 1);
-                        ++k;
-                    }
-        return SIM_OK;
-    } catch (const Error &e) {
-        s->err = e.msg;
-        return e.code;
+    const int64_t total = (int64_t)s->spikes.size();
+    if (n_total) *n_total = total;
+    if (!out) return SIM_OK;  // count query
+    if (cap < total) {
+        s->err = "spike buffer too small";
+        return SIM_EINVAL;
     }
+    if (total) std::memcpy(out, s->spikes.data(), sizeof(sim_spike_t) * (size_t)total);
+    return SIM_OK;
 }
 
 int sim_neuron_timings(sim_t *s, double *out, int64_t cap, int32_t reset) {
     if (!s || !out || cap < s->N) return SIM_EINVAL;
+    if (!need_device(s)) return SIM_ESTATE;
     try {
         std::vector<uint64_t> t(s->packs.size());
         HIPCHK(hipMemcpy(t.data(), s->d_ptime.p, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost));
@@ -1501,6 +1919,7 @@ int sim_features(sim_t *s, float *out, int64_t cap) {
 
 int sim_set_kernel_timing(sim_t *s, int32_t on) {
     if (!s) return SIM_EINVAL;
+    if (!need_device(s)) return SIM_ESTATE;
     try {
         HIPCHK(hipStreamSynchronize(s->stream));
         ktimer_reset(s);
@@ -1515,15 +1934,18 @@ int sim_set_kernel_timing(sim_t *s, int32_t on) {
     for (int c = 0; c < kClasses; ++c) {
         s->kt_cls_ms[c] = 0;
         s->kt_cls_n[c] = 0;
+        s->kt_cls_upd[c] = 0;
     }
     return SIM_OK;
 }
 
-int sim_class_time(sim_t *s, int32_t cls, double *ms, int64_t *launches, int64_t *comps) {
+int sim_class_time(sim_t *s, int32_t cls, double *ms, int64_t *launches, int64_t *comps,
+                   int64_t *updates) {
     if (!s || cls < 0 || cls >= kClasses) return SIM_EINVAL;
     if (ms) *ms = s->kt_cls_ms[cls];
     if (launches) *launches = s->kt_cls_n[cls];
     if (comps) *comps = s->cls_comps[cls];
+    if (updates) *updates = s->kt_cls_upd[cls];
     return SIM_OK;
 }
 
@@ -1545,8 +1967,12 @@ void sim_destroy(sim_t *s) {
     fr(s->d_e); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
     fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
     fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
-    fr(s->d_sseg); fr(s->d_chl); fr(s->d_fw); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
-    fr(s->d_hist); fr(s->d_ptime); fr(s->d_ktimer);
+    fr(s->d_sseg); fr(s->d_chl); fr(s->d_fw); fr(s->d_cit); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
+    fr(s->d_ring); fr(s->d_ptime); fr(s->d_ktimer);
+    for (int k = 0; k < 2; ++k) {
+        if (s->h_stage[k]) (void)hipHostFree(s->h_stage[k]);
+        if (s->ev_stage[k]) (void)hipEventDestroy(s->ev_stage[k]);
+    }
     if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
     for (int c = 1; c < kClasses; ++c) {
         if (s->ev_join[c]) (void)hipEventDestroy(s->ev_join[c]);

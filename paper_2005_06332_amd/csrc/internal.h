@@ -50,12 +50,25 @@ struct PackDesc {
     int32_t neur0, nneur;  // packed neuron range
     int32_t br0, nbr;      // branch table range (records and forward order)
     int32_t ch0;           // child list / child contribution offset
-    int32_t lv0;           // level offsets: nbw+1 backward then nfw+1 forward
+    int32_t lv0;           // level offsets: nbw+1 backward, nfw+1 forward, then
+                           // nrnd+1 contraction round offsets
     int32_t nbw, nfw;      // number of height / depth levels
     int32_t global_mem;    // 0: state in LDS; k > 0: state in global scratch slice k-1
     int32_t nch;           // child list entries
     int32_t tbytes;        // bytes of staged tables (always in LDS)
+    int32_t it0, nrnd;     // contraction solver: first item, rounds (0: other solvers)
 };
+
+// Contraction solver item, one per compartment of a pack: bits 0..14 the
+// eliminated compartment k, bit 15 set when n1 is k's current parent, bits
+// 16..31 n1, bits 32..47 n2 (pack-local; kNoNb when absent). Items are
+// stored by round; round r of a pack spans items rof[r] .. rof[r+1]-1.
+constexpr uint32_t kNoNb = 0xFFFF;
+__host__ __device__ inline uint64_t make_item(uint32_t k, bool n1_parent, uint32_t n1,
+                                              uint32_t n2) {
+    return (uint64_t)(k & 0x7FFFu) | (n1_parent ? 0x8000ull : 0ull) | ((uint64_t)n1 << 16) |
+           ((uint64_t)n2 << 32);
+}
 
 // Everything the epoch kernel reads or writes. T is the gating precision.
 struct EpochArgs {
@@ -85,9 +98,13 @@ struct EpochArgs {
     const uint16_t *fw;  // forward-sweep order: record ids by depth, longest chains first
     const uint16_t *chl;
     const int32_t *lvl;
-    // spike history: hist[epoch * n_neurons + input id] = bit t set when the
-    // neuron spiked at step epoch*E + t + 1
-    uint64_t *hist;
+    const uint64_t *cit;   // contraction items (by pack, by round); the round
+                           // offsets follow a pack's level offsets in lvl
+    // spike history, a ring of ring_rows epochs: ring[(epoch mod ring_rows)
+    // * n_neurons + input id] = bit t set when the neuron spiked at step
+    // epoch*E + t + 1. ring_rows exceeds the epochs any delay looks back.
+    uint64_t *ring;
+    int32_t ring_rows;
     int32_t n_neurons;
     int32_t E;
     const int64_t *epoch_ptr;  // when non-null, the epoch index is read here
@@ -124,13 +141,17 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
 // Bytes of the pack's tables staged in LDS next to the state: branch records,
 // synapse weights (T), level offsets, the forward order, child list, synapse
 // targets and run lengths. Must match the carve-up in the kernel.
+// The contraction solver adds its items (8 B per compartment) and round
+// offsets (nrnd + 1 ints); nrnd = 0 for the other solvers.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
-                                                    int64_t nsyn) {
+                                                    int64_t nsyn, int64_t ncomp = 0,
+                                                    int64_t nrnd = 0) {
     int64_t b = (int64_t)sizeof(Branch) * nbr;
     b += (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
     b += 2 * nbr + 2 * nch + 2 * 2 * nsyn;
+    if (nrnd > 0) b = (b + 7) / 8 * 8 + 8 * ncomp + 4 * (nrnd + 1);
     return (b + 15) / 16 * 16;
 }
 
@@ -149,6 +170,7 @@ struct SetupArgs {
 // Launchers (kernels.hip).
 hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s);
 // solver: 0 = exact operation order of the elimination, 1 = division-free
+// homogeneous form, 2 = tree contraction
 hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg, int threads,
                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);

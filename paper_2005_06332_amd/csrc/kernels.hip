@@ -275,17 +275,19 @@ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
 
 // Events of synapse (pre, delay) in the steps epoch*E + t, t in [0, E): bit t
 // set when `pre` spiked at step epoch*E + t - delay (>= 1). Reads only
-// epochs before `epoch` because delay >= E.
-__device__ __forceinline__ uint64_t event_mask(const uint64_t *hist, int32_t N, int32_t E,
-                                               int64_t epoch, int32_t pre, int32_t delay) {
+// epochs before `epoch` because delay >= E, and at most
+// ceil((delay + 1) / E) epochs back, which the ring still holds.
+__device__ __forceinline__ uint64_t event_mask(const uint64_t *ring, int32_t R, int32_t N,
+                                               int32_t E, int64_t epoch, int32_t pre,
+                                               int32_t delay) {
     const int64_t g0 = epoch * E - delay - 1;  // history bit of t = 0
     if (g0 + E - 1 < 0) return 0;
     const int64_t w0 = floor_div(g0, E);
     const int off = (int)(g0 - w0 * E);
-    const uint64_t lo = (w0 >= 0) ? hist[w0 * N + pre] : 0ull;
+    const uint64_t lo = (w0 >= 0) ? ring[(w0 % R) * N + pre] : 0ull;
     uint64_t m = lo >> off;
     if (off > 0) {
-        const uint64_t hi = (w0 + 1 >= 0) ? hist[(w0 + 1) * N + pre] : 0ull;
+        const uint64_t hi = (w0 + 1 >= 0) ? ring[((w0 + 1) % R) * N + pre] : 0ull;
         m |= hi << (E - off);
     }
     if (E < 64) m &= (1ull << E) - 1ull;
@@ -387,17 +389,23 @@ __device__ __forceinline__ void sweep_back_blk(double *__restrict__ D, double *_
             P = Pn;
             S = Sn;
         };
-        if (b.nchild == 2) {
-            merge(b.cb[1]);
-            merge(b.cb[0]);
-        } else {
-            for (int c = b.nchild - 1; c >= 0; --c) merge(chl[b.child0 + c]);
-        }
-        if (b.nchild > 0) {
+        auto rescale = [&]() {
             const int x = -__builtin_amdgcn_frexp_exp(P);
             P = __builtin_amdgcn_ldexp(P, x);
             q = __builtin_amdgcn_ldexp(q, x);
             S = __builtin_amdgcn_ldexp(S, x);
+        };
+        if (b.nchild == 2) {
+            merge(b.cb[1]);
+            merge(b.cb[0]);
+            rescale();
+        } else {
+            // any fan-out: rescaled after every child, so that a node with
+            // many children cannot drive the products out of range
+            for (int c = b.nchild - 1; c >= 0; --c) {
+                merge(chl[b.child0 + c]);
+                rescale();
+            }
         }
     } else {
         auto contribution = [&](const int j, double &cd, double &cr) {
@@ -536,6 +544,53 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
     }
 }
 
+// Tree contraction (the third solver). Eliminating compartment k with its
+// current neighbours n1, n2 (couplings a1, a2) is one step of Gaussian
+// elimination: each neighbour's diagonal loses a^2/d_k and its right-hand
+// side a r_k/d_k; when both exist, n2 is linked to n1 with the coupling
+// -a1 a2/d_k. Every compartment keeps in EW the coupling to its current
+// parent; the couplings of k needed later are g1 = a1/d_k (into EW[k]) and
+// g2 = a2/d_k (into V[k], free during the solve), with h = r_k/d_k into
+// R[k]. A round's eliminations are at least three apart in the current
+// tree, so each survivor is written by one lane at most.
+__device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
+                                              double *__restrict__ V, double *__restrict__ EW,
+                                              const uint64_t it) {
+    const int k = (int)(it & 0x7FFFu);
+    const bool up = (it >> 15) & 1u;
+    const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
+    const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
+    const double y = rcp_nr(D[k]);
+    const double a1 = h1 ? EW[up ? k : (int)n1] : 0.0;
+    const double a2 = h2 ? EW[n2] : 0.0;
+    const double h = R[k] * y, g1 = a1 * y, g2 = a2 * y;
+    if (h1) {
+        D[n1] = __builtin_fma(-a1, g1, D[n1]);
+        R[n1] = __builtin_fma(-a1, h, R[n1]);
+    }
+    if (h2) {
+        D[n2] = __builtin_fma(-a2, g2, D[n2]);
+        R[n2] = __builtin_fma(-a2, h, R[n2]);
+        if (h1) EW[n2] = -(a1 * g2);
+    }
+    R[k] = h;
+    EW[k] = g1;
+    V[k] = g2;
+}
+
+// Back substitution of k, its neighbours at elimination time solved already:
+// x_k = h - g1 x_n1 - g2 x_n2.
+__device__ __forceinline__ void contract_subst(const double *__restrict__ R,
+                                               double *__restrict__ V,
+                                               const double *__restrict__ EW, const uint64_t it) {
+    const int k = (int)(it & 0x7FFFu);
+    const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
+    double x = R[k];
+    if (n1 != kNoNb) x = __builtin_fma(-EW[k], V[n1], x);
+    if (n2 != kNoNb) x = __builtin_fma(-V[k], V[n2], x);
+    V[k] = x;
+}
+
 struct Consts {
     double omt, vth, ginv;
 };
@@ -618,6 +673,8 @@ struct Tables {
     T *sw;
     int32_t *lvl;
     uint16_t *chl, *scomp, *sseg;
+    uint64_t *cit;  // contraction items, then round offsets
+    int32_t *crof;
 };
 
 template <typename T>
@@ -632,6 +689,10 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
     t.chl = t.fw + pk.nbr;
     t.scomp = t.chl + pk.nch;
     t.sseg = t.scomp + pk.nsyn;
+    char *q = (char *)(t.sseg + pk.nsyn);
+    q = smem + (((q - smem) + 7) / 8) * 8;
+    t.cit = (uint64_t *)q;
+    t.crof = (int32_t *)(t.cit + (pk.nrnd > 0 ? pk.ncomp : 0));
     return t;
 }
 
@@ -642,9 +703,11 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
 // In the sweeps the branches of a level go to consecutive lanes (sorted by
 // length on the host), so one wave instruction advances as many chains as
 // the level has branches.
-template <typename T, bool kFast>
+template <typename T, int kSolve>
 __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
                                          char *base, int64_t epoch) {
+    constexpr bool kFast = kSolve == 1;
+    constexpr bool kContract = kSolve == 2;
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
     const int slot = tid;
@@ -672,6 +735,12 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             tb.scomp[k] = a.scomp[s0 + k];
             tb.sseg[k] = a.sseg[s0 + k];
         }
+        if constexpr (kContract) {
+            const uint64_t *gci = a.cit + pk.it0;
+            for (int k = tid; k < n; k += NT) tb.cit[k] = gci[k];
+            const int32_t *gro = a.lvl + pk.lv0 + pk.nbw + pk.nfw + 2;
+            for (int k = tid; k <= pk.nrnd; k += NT) tb.crof[k] = gro[k];
+        }
     }
     double *__restrict__ V = st.V;
     double *__restrict__ R = st.R;
@@ -695,15 +764,20 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const Consts cs{a.omt, a.v_thresh, a.ginv};
     const int t0 = a.t0, t1 = a.t1;
 
+    // the contraction solver keeps the working couplings in the Eo slot and
+    // reads the constant off-diagonal from global memory
+    const double *Ec = kContract ? a.e + c0 : Eo;
+
     // ---- load state -------------------------------------------------------
     for (int i = tid; i < n; i += NT) {
         V[i] = a.V[c0 + i];
-        Eo[i] = a.e[c0 + i];
+        if constexpr (!kContract) Eo[i] = a.e[c0 + i];
         R[i] = 0.0;  // synaptic conductance of compartment i in phases A/B
     }
     for (int k = tid; k < ns; k += NT) {
         SG[k] = ((const T *)a.sg)[s0 + k];
-        st.SM[k] = event_mask(a.hist, a.n_neurons, a.E, epoch, a.spre[s0 + k], a.sdelay[s0 + k]);
+        st.SM[k] = event_mask(a.ring, a.ring_rows, a.n_neurons, a.E, epoch, a.spre[s0 + k],
+                              a.sdelay[s0 + k]);
     }
     for (int k = tid; k < nn; k += NT) {
         st.VO[k] = a.V[c0 + a.ndet[pk.neur0 + k]];
@@ -732,11 +806,32 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 
         // ---- B: membrane terms and assembly --------------------------------
 #pragma unroll 2
-        for (int i = tid; i < n; i += NT)
-            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl, niext,
+        for (int i = tid; i < n; i += NT) {
+            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Ec, br, chl, niext,
                         pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
+            if constexpr (kContract) Eo[i] = Ec[i];
+        }
         __syncthreads();
         MMH_PHASE(2);
+
+        if constexpr (kContract) {
+            // ---- C': contraction rounds, then back substitution ------------
+            // (V^n is no longer needed: detection keeps its own copy)
+            const uint64_t *cit = tb.cit;
+            const int32_t *rof = tb.crof;
+            for (int r = 0; r < pk.nrnd; ++r) {
+                for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
+                    contract_elim(D, R, V, Eo, cit[q2]);
+                __syncthreads();
+            }
+            MMH_PHASE(3);
+            for (int r = pk.nrnd - 1; r >= 0; --r) {
+                for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
+                    contract_subst(R, V, Eo, cit[q2]);
+                __syncthreads();
+            }
+            MMH_PHASE(4);
+        } else {
 
         // ---- C: backward sweep by height -----------------------------------
         // (V^n is no longer needed: detection keeps its own copy, so the V
@@ -787,6 +882,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             }
         }
         MMH_PHASE(4);
+        }  // level-synchronous solvers
 
         // ---- E: gates at V^{n+1}; detection --------------------------------
 #pragma unroll 1
@@ -815,16 +911,20 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         T *osg = (T *)a.sg;
         for (int k = tid; k < ns; k += NT) osg[s0 + k] = q * SG[k];
     }
+    // the epoch's ring row: a launch that starts the epoch replaces the row's
+    // previous contents (an epoch ring_rows earlier); a launch that continues
+    // it adds its steps' bits
     for (int k = tid; k < nn; k += NT) {
-        if (st.SP[k]) {
-            uint64_t *w = a.hist + epoch * a.n_neurons + a.nid[pk.neur0 + k];
+        uint64_t *w = a.ring + (epoch % a.ring_rows) * a.n_neurons + a.nid[pk.neur0 + k];
+        if (t0 == 0)
+            *w = st.SP[k];
+        else if (st.SP[k])
             *w = *w | st.SP[k];
-        }
     }
     MMH_PHASE(6);
 }
 
-template <typename T, bool kFast>
+template <typename T, int kSolve>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
     k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
@@ -849,10 +949,10 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         // visibly derived from the shared array and its accesses compile to
         // LDS instructions rather than generic (flat) ones
         if (pk.global_mem)
-            run_pack<T, kFast>(a, pk, smem,
-                               a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch);
+            run_pack<T, kSolve>(a, pk, smem,
+                                a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch);
         else
-            run_pack<T, kFast>(a, pk, smem, smem + pk.tbytes, epoch);
+            run_pack<T, kSolve>(a, pk, smem, smem + pk.tbytes, epoch);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
@@ -921,21 +1021,26 @@ hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg,
     const dim3 g(n_wg), b(threads);
     if (precision == 0) {
         if (solver == 0)
-            hipLaunchKernelGGL((k_epoch<double, false>), g, b, lds_bytes, s, a);
+            hipLaunchKernelGGL((k_epoch<double, 0>), g, b, lds_bytes, s, a);
+        else if (solver == 1)
+            hipLaunchKernelGGL((k_epoch<double, 1>), g, b, lds_bytes, s, a);
         else
-            hipLaunchKernelGGL((k_epoch<double, true>), g, b, lds_bytes, s, a);
+            hipLaunchKernelGGL((k_epoch<double, 2>), g, b, lds_bytes, s, a);
     } else {
         if (solver == 0)
-            hipLaunchKernelGGL((k_epoch<float, false>), g, b, lds_bytes, s, a);
+            hipLaunchKernelGGL((k_epoch<float, 0>), g, b, lds_bytes, s, a);
+        else if (solver == 1)
+            hipLaunchKernelGGL((k_epoch<float, 1>), g, b, lds_bytes, s, a);
         else
-            hipLaunchKernelGGL((k_epoch<float, true>), g, b, lds_bytes, s, a);
+            hipLaunchKernelGGL((k_epoch<float, 2>), g, b, lds_bytes, s, a);
     }
     return hipGetLastError();
 }
 
 hipError_t set_epoch_lds_limit(int bytes) {
-    const void *fns[] = {(const void *)k_epoch<double, false>, (const void *)k_epoch<double, true>,
-                         (const void *)k_epoch<float, false>, (const void *)k_epoch<float, true>};
+    const void *fns[] = {(const void *)k_epoch<double, 0>, (const void *)k_epoch<double, 1>,
+                         (const void *)k_epoch<double, 2>, (const void *)k_epoch<float, 0>,
+                         (const void *)k_epoch<float, 1>, (const void *)k_epoch<float, 2>};
     for (const void *f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -49,17 +49,22 @@ def imbalance(n_neurons: int = 10000, steps: int = 400, warmup: int = 40, seed: 
     model = costmodel.load_or_train()
     runs = {
         "mono_plain": _time(mono, S.PACK_PLAIN, steps, warmup, solver),
+        "mono_count": _time(mono, S.PACK_COUNT, steps, warmup, solver),
         "multi_plain": _time(multi, S.PACK_PLAIN, steps, warmup, solver),
         "multi_count": _time(multi, S.PACK_COUNT, steps, warmup, solver),
         "multi_learned": _time(multi, S.PACK_LEARNED, steps, warmup, solver, model),
     }
-    base = runs["mono_plain"]["ns_per_update"]
-    for r in runs.values():
-        r["extra_vs_mono"] = r["ns_per_update"] / base - 1.0
+    for base in ("mono_plain", "mono_count"):
+        b = runs[base]["ns_per_update"]
+        for r in runs.values():
+            r[f"extra_vs_{base}"] = r["ns_per_update"] / b - 1.0
     sizes = multi["n_comp"]
     return dict(experiment="mono vs multi-morphology (paper Section 4)", neurons=n_neurons,
                 steps=steps, group_sizes=sorted(set(int(x) for x in sizes)),
-                mono_size=int(mono["n_comp"][0]), runs=runs)
+                group_mean=float(sizes.mean()), mono_size=int(mono["n_comp"][0]),
+                compartments=dict(mono=int(mono["comp_off"][-1]),
+                                  multi=int(multi["comp_off"][-1])),
+                runs=runs)
 
 
 def main():

@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("MMHINES_LIB") or os.path.join(HERE, "libmmhines.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
 FP64, FP32_GATING = 0, 1
-SOLVE_EXACT, SOLVE_FAST = 0, 1
+SOLVE_EXACT, SOLVE_FAST, SOLVE_CONTRACT = 0, 1, 2
 PACK_PLAIN, PACK_COUNT, PACK_LEARNED = 0, 1, 2
 SCHED_AUTO, SCHED_PERSISTENT, SCHED_DISPATCH = 0, 1, 2
 N_FEATURES = 16
@@ -29,6 +29,8 @@ EXPORTS = (
     "sim_set_kernel_timing", "sim_kernel_time", "sim_class_time", "sim_config_string",
     "sim_destroy", "sim_last_error", "sim_mlp_nparams", "sim_mlp_init",
     "sim_mlp_forward", "sim_mlp_loss_grad", "sim_mlp_train",
+    "sim_plan_create", "sim_pack_count", "sim_pack_info", "sim_pack_neurons",
+    "sim_class_launch", "sim_workgroup_packs", "sim_contraction_schedule",
 )
 
 
@@ -69,6 +71,16 @@ class Synapses(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("pre", C.c_void_p), ("post", C.c_void_p),
         ("post_comp", C.c_void_p), ("delay_steps", C.c_void_p), ("weight_uS", C.c_void_p),
+    ]
+
+
+class PackInfo(C.Structure):
+    _fields_ = [
+        ("first_position", C.c_int32), ("n_neurons", C.c_int32), ("n_comp", C.c_int32),
+        ("n_syn", C.c_int32), ("n_branches", C.c_int32), ("size_class", C.c_int32),
+        ("in_global", C.c_int32), ("n_rounds", C.c_int32), ("n_levels", C.c_int32),
+        ("n_child_entries", C.c_int32), ("table_bytes", C.c_int64),
+        ("state_bytes", C.c_int64), ("cost", C.c_double),
     ]
 
 
@@ -115,13 +127,26 @@ def lib():
         L.sim_set_kernel_timing.argtypes = [P, C.c_int32]
         L.sim_kernel_time.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.sim_class_time.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64),
-                                     C.POINTER(C.c_int64)]
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sim_config_string.argtypes = [P]
         L.sim_config_string.restype = C.c_char_p
         L.sim_destroy.argtypes = [P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = [P]
         L.sim_last_error.restype = C.c_char_p
+        L.sim_plan_create.argtypes = [C.POINTER(Params), C.POINTER(Morphology),
+                                      C.POINTER(Channels), C.POINTER(Synapses), C.c_int32,
+                                      C.c_int32, C.POINTER(C.c_void_p)]
+        L.sim_pack_count.argtypes = [P]
+        L.sim_pack_count.restype = C.c_int32
+        L.sim_pack_info.argtypes = [P, C.c_int32, C.POINTER(PackInfo)]
+        L.sim_pack_neurons.argtypes = [P, C.c_int32, P, C.c_int64]
+        L.sim_class_launch.argtypes = [P, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.sim_workgroup_packs.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int64,
+                                          C.POINTER(C.c_int32)]
+        L.sim_contraction_schedule.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64,
+                                               C.POINTER(C.c_int32)]
         L.sim_mlp_nparams.restype = C.c_int64
         L.sim_mlp_init.argtypes = [P, P, P, C.c_int64, C.c_uint64]
         L.sim_mlp_forward.argtypes = [P, P, C.c_int64, P]
@@ -130,7 +155,9 @@ def lib():
         for f in ("sim_read_voltages", "sim_read_gates", "sim_read_conductances", "sim_spikes",
                   "sim_neuron_timings", "sim_features", "sim_set_kernel_timing",
                   "sim_kernel_time", "sim_class_time", "sim_mlp_init", "sim_mlp_forward",
-                  "sim_mlp_loss_grad", "sim_mlp_train"):
+                  "sim_mlp_loss_grad", "sim_mlp_train", "sim_plan_create", "sim_pack_info",
+                  "sim_pack_neurons", "sim_class_launch", "sim_workgroup_packs",
+                  "sim_contraction_schedule"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -160,7 +187,9 @@ class Simulation:
                  pack_comps: int = 0, lds_comps: int = 0, use_graph: bool = True,
                  record_timings: bool = False, cost_model: np.ndarray | None = None,
                  epoch_steps: int = 0, stream: int | None = None, solver: int | None = None,
-                 lds_classes: int = 0):
+                 lds_classes: int = 0, plan: tuple | None = None):
+        """plan = (lds_bytes_per_cu, n_cu): lay the problem out on the host
+        only (sim_plan_create), for the introspection calls."""
         L = lib()
         pr = prob["params"]
         ch = prob["channels"]
@@ -198,7 +227,11 @@ class Simulation:
         SY = Synapses(self.S, _p(keep["syn_pre"]), _p(keep["syn_post"]), _p(keep["syn_comp"]),
                       _p(keep["syn_delay"]), _p(keep["syn_w"]))
         h = C.c_void_p()
-        rc = L.sim_create(C.byref(P), C.byref(M), C.byref(CH), C.byref(SY), C.byref(h))
+        if plan is None:
+            rc = L.sim_create(C.byref(P), C.byref(M), C.byref(CH), C.byref(SY), C.byref(h))
+        else:
+            rc = L.sim_plan_create(C.byref(P), C.byref(M), C.byref(CH), C.byref(SY),
+                                   int(plan[0]), int(plan[1]), C.byref(h))
         _check(rc, None)
         self._h = h
 
@@ -265,6 +298,49 @@ class Simulation:
         _check(lib().sim_features(self._h, _p(out), out.size), self._h)
         return out
 
+    # ---- layout introspection --------------------------------------------
+
+    def pack_count(self) -> int:
+        return int(lib().sim_pack_count(self._h))
+
+    def pack_info(self, pack: int) -> dict:
+        info = PackInfo()
+        _check(lib().sim_pack_info(self._h, int(pack), C.byref(info)), self._h)
+        return {name: getattr(info, name) for name, _ in PackInfo._fields_}
+
+    def pack_neurons(self, pack: int) -> np.ndarray:
+        n = self.pack_info(pack)["n_neurons"]
+        out = np.empty(n, np.int32)
+        _check(lib().sim_pack_neurons(self._h, int(pack), _p(out), n), self._h)
+        return out
+
+    def class_launch(self, cls: int):
+        """(workgroups, threads, LDS bytes) of size class cls."""
+        n, t, b = C.c_int32(0), C.c_int32(0), C.c_int64(0)
+        _check(lib().sim_class_launch(self._h, int(cls), C.byref(n), C.byref(t), C.byref(b)),
+               self._h)
+        return n.value, t.value, b.value
+
+    def workgroup_packs(self, cls: int, wg: int) -> np.ndarray:
+        n = C.c_int32(0)
+        _check(lib().sim_workgroup_packs(self._h, int(cls), int(wg), None, 0, C.byref(n)),
+               self._h)
+        out = np.empty(n.value, np.int32)
+        _check(lib().sim_workgroup_packs(self._h, int(cls), int(wg), _p(out), out.size,
+                                         C.byref(n)), self._h)
+        return out
+
+    def contraction_schedule(self, neuron: int, n_comp: int):
+        """(items [n_comp, 4] = (k, n1, n2, n1_is_parent), round offsets)."""
+        nr = C.c_int32(0)
+        _check(lib().sim_contraction_schedule(self._h, int(neuron), None, 0, None, 0,
+                                              C.byref(nr)), self._h)
+        items = np.empty((n_comp, 4), np.int32)
+        ro = np.empty(nr.value + 1, np.int32)
+        _check(lib().sim_contraction_schedule(self._h, int(neuron), _p(items), items.size,
+                                              _p(ro), ro.size, C.byref(nr)), self._h)
+        return items, ro
+
     def set_kernel_timing(self, on: bool) -> None:
         _check(lib().sim_set_kernel_timing(self._h, int(on)), self._h)
 
@@ -275,10 +351,12 @@ class Simulation:
         return ms.value, n.value
 
     def class_time(self, cls: int):
-        """(total ms, launches, compartments per step) of size class cls."""
-        ms, n, c = C.c_double(0), C.c_int64(0), C.c_int64(0)
-        _check(lib().sim_class_time(self._h, cls, C.byref(ms), C.byref(n), C.byref(c)), self._h)
-        return ms.value, n.value, c.value
+        """(total ms, launches, compartments per step, compartment-updates) of
+        size class cls over the timed launches."""
+        ms, n, c, u = C.c_double(0), C.c_int64(0), C.c_int64(0), C.c_int64(0)
+        _check(lib().sim_class_time(self._h, cls, C.byref(ms), C.byref(n), C.byref(c),
+                                    C.byref(u)), self._h)
+        return ms.value, n.value, c.value, u.value
 
 
 # ---- cost model ---------------------------------------------------------------

@@ -277,20 +277,47 @@ def mini(seed: int = 11, n_neurons: int = 48, precision: int = 1,
                             IEXT_MAX_NA["mini"], precision)
 
 
+def group_sizes(rng, count: int = 20, spread: int = 700, mean: int = 300,
+                smallest: int = 12) -> np.ndarray:
+    """`count` random neuron sizes whose largest minus smallest is exactly
+    `spread`, whose mean is exactly `mean` and whose smallest is at least
+    `smallest` (the size group of the paper's Section 4 experiment).
+
+    The smallest and largest members sit at m and m + spread; the others are
+    m + spread * x with x ~ Beta(1, 2) (skewed small, so that the mean can be
+    reached with m >= smallest), redrawn until that holds; integer rounding
+    is then corrected by +-1 steps on the inner members so that the sum is
+    exactly count * mean."""
+    while True:
+        x = np.concatenate([[0.0, 1.0], rng.beta(1.0, 2.0, count - 2)])
+        m = mean - spread * x.mean()
+        if m >= smallest:
+            break
+    lo = int(np.rint(m))
+    sizes = np.concatenate([[lo, lo + spread],
+                            np.rint(lo + spread * x[2:]).astype(np.int64)]).astype(np.int64)
+    sizes[2:] = np.clip(sizes[2:], lo, lo + spread)
+    diff = count * mean - int(sizes.sum())
+    k = 2
+    while diff != 0:
+        step = 1 if diff > 0 else -1
+        if lo < sizes[k] + step < lo + spread:
+            sizes[k] += step
+            diff -= step
+        k = 2 + (k - 1) % (count - 2)
+    return sizes
+
+
 def size_group(seed: int = 7, n_neurons: int = 10000, mono: bool = False,
                precision: int = 1, n_steps: int = 400) -> dict:
-    """The paper's Section-4 imbalance test: a group of 20 neurons with random
-    sizes whose spread (max - min) is 700 compartments and whose mean is 300
-    (shifted up if needed so that every size is at least 12); each of the
-    n_neurons neurons is a copy of a member drawn uniformly from the group.
-    mono: every neuron is a copy of one neuron of the mean size (300). The
-    trees follow the cfg3 recipe with at most 32 branches."""
+    """The paper's Section-4 imbalance test: a group of 20 neurons whose sizes
+    have a spread (max - min) of exactly 700 compartments and a mean of
+    exactly 300 (group_sizes); the network holds n_neurons / 20 copies of each
+    member in a random order, so its compartment total equals that of the
+    mono-morphology network, n_neurons copies of one 300-compartment neuron.
+    The trees follow the cfg3 recipe with at most 32 branches."""
     rng = np.random.default_rng(seed)
-    g = rng.random(20)
-    g = (g - g.min()) / (g.max() - g.min()) * 700.0
-    g = g - g.mean() + 300.0
-    lo_shift = max(0.0, 12.0 - g.min())
-    g = np.rint(g + lo_shift).astype(np.int64)
+    g = group_sizes(rng)
 
     def one(n):
         B = max(2, int(min(32, 2 * ((n - 1) // 4))))
@@ -305,11 +332,41 @@ def size_group(seed: int = 7, n_neurons: int = 10000, mono: bool = False,
         morphs = [proto] * n_neurons
     else:
         group = [one(int(n)) for n in g]
-        pick = rng.integers(0, 20, n_neurons)
+        pick = np.resize(np.arange(20), n_neurons)
+        rng.shuffle(pick)
         morphs = [group[k] for k in pick]
     return _assemble("size_group_mono" if mono else "size_group", seed, morphs,
                      _hh_all, rng, 100, lambda s: np.full(s, 40), 2.0,
                      n_steps, precision)
+
+
+def star_network(seed: int = 31, n_neurons: int = 16, fanout=(64, 5), branch_len: int = 3,
+                 precision: int = 1, n_steps: int = 200) -> dict:
+    """Neurons whose soma carries many unbranched dendrites (neuron j has
+    fanout[j % len(fanout)] children of branch_len compartments, diameters as
+    in the cfg3 recipe): nodes of very high fan-out, a degenerate case of the
+    tree solve. HH everywhere, 12 synapses per neuron, delay 40 steps."""
+    rng = np.random.default_rng(seed)
+    morphs = []
+    for j in range(n_neurons):
+        B = int(fanout[j % len(fanout)])
+        n = 1 + B * branch_len
+        parent = np.empty(n, np.int32)
+        parent[0] = -1
+        length = np.full(n, DEND_L_UM)
+        length[0] = SOMA_L_UM
+        diam = np.empty(n)
+        diam[0] = SOMA_D_UM
+        d0, d1 = _taper(rng, B)
+        for b in range(B):
+            b0 = 1 + b * branch_len
+            parent[b0] = 0
+            parent[b0 + 1:b0 + branch_len] = np.arange(b0, b0 + branch_len - 1)
+            frac = (np.arange(branch_len) + 0.5) / branch_len
+            diam[b0:b0 + branch_len] = d0[b] + (d1[b] - d0[b]) * frac
+        morphs.append((parent, length, diam))
+    return _assemble("star", seed, morphs, _hh_all, rng, 12, lambda s: np.full(s, 40),
+                     IEXT_MAX_NA["mini"], n_steps, precision)
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

@@ -6,7 +6,8 @@ Voltage tolerances:
 - exact solver (the elimination in the oracle's operation order): 1e-9 mV in
   both precision modes; in practice the results are bitwise equal, and the
   tests report how many voltages differ at all.
-- fast solver (division-free homogeneous elimination), FP64: 1e-9 mV. Its
+- fast solver (division-free homogeneous elimination) and contraction
+  solver (tree contraction), FP64: 1e-9 mV. Its
   per-step rounding differs from the oracle's by a few ulps of V (about
   1e-14 mV), measured at 2.6e-11 mV after 200 steps of the full network.
 - fast solver, FP32 gating: 1e-4 mV. The gates see (float)V; a V that
@@ -30,7 +31,10 @@ TOL_FAST_FP32_MV = 1e-4
 
 
 def tol(precision, solver):
-    return TOL_FAST_FP32_MV if (solver == 1 and precision == 1) else TOL_MV
+    """Exact solver: 1e-9 mV. The reassociated solvers (fast: homogeneous
+    form; contract: tree contraction): 1e-9 mV in FP64, 1e-4 mV with FP32
+    gating."""
+    return TOL_FAST_FP32_MV if (solver != 0 and precision == 1) else TOL_MV
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +79,7 @@ def run_pair(S, orc, prob, steps, precision, chunks=None, **kw):
     return out, (vr, sr, (mr, hr, nr), gr)
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_config1_matches_oracle(S, orc, precision, solver):
     prob = W.config1()
@@ -89,7 +93,7 @@ def test_config1_matches_oracle(S, orc, precision, solver):
     assert len(sr) > 0
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("packing,sched,pack_comps,lds", [
     (0, 0, 0, 0),        # plain, one workgroup per pack
@@ -109,7 +113,7 @@ def test_multimorphology_matches_oracle(S, orc, precision, solver, packing, sche
     assert len(sr) > 0
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_partial_epochs_and_graph_replay_match(S, orc, solver):
     prob = W.mini(seed=13, n_steps=300, delay_lo=40, delay_hi=90)
     chunks = [7, 33, 1, 79, 80, 100]
@@ -168,7 +172,7 @@ def test_single_compartment_and_tiny_neurons(S, orc):
     compare("mini with n=1 neurons", v, vr, s, sr)
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_packing_and_launch_variants_are_bitwise_identical(S, solver):
     prob = W.mini(seed=29, n_steps=200, n_neurons=96)
     base = None
@@ -215,8 +219,8 @@ def test_full_size_multimorphology_matches_oracle(S, orc):
     steps = 200
     say(f"case full cfg3 N={prob['n_comp'].shape[0]} C={int(prob['comp_off'][-1])} steps={steps}")
     outs = {}
-    for solver in (1, 0):
-        with S.Simulation(prob, packing=S.PACK_COUNT, autotune=(solver == 1),
+    for solver in (1, 0, 2):
+        with S.Simulation(prob, packing=S.PACK_COUNT, autotune=(solver != 0),
                           solver=solver) as g:
             say("  config:", g.config)
             g.step(steps)
@@ -233,11 +237,15 @@ def test_full_size_multimorphology_matches_oracle(S, orc):
     compare("full cfg3 fast vs FP32-gating oracle", v, vr, s, sr, TOL_FAST_FP32_MV)
     compare("full cfg3 fast vs FP64 oracle", v, vr64, s, sr64, 1e-2)
     compare("full cfg3 exact vs FP32-gating oracle", outs[0][0], vr, outs[0][1], sr)
+    compare("full cfg3 contract vs FP32-gating oracle", outs[2][0], vr, outs[2][1], sr,
+            TOL_FAST_FP32_MV)
+    compare("full cfg3 contract vs FP64 oracle", outs[2][0], vr64, outs[2][1], sr64, 1e-2)
     assert len(sr) > 1000
 
 
 @pytest.mark.parametrize("cfg,precision,solver,steps", [
-    (2, 0, 0, 80), (2, 0, 1, 80), (4, 1, 1, 80), (4, 1, 0, 80), (5, 1, 1, 40),
+    (2, 0, 0, 80), (2, 0, 1, 80), (2, 0, 2, 80), (4, 1, 1, 80), (4, 1, 0, 80), (4, 1, 2, 80),
+    (5, 1, 1, 40), (5, 1, 2, 40),
 ])
 def test_other_full_size_configs_match_oracle(S, orc, cfg, precision, solver, steps):
     """The other full-size workloads against the oracle in the same precision,
@@ -255,7 +263,7 @@ def test_other_full_size_configs_match_oracle(S, orc, cfg, precision, solver, st
             tol(precision, solver))
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_full_length_replay_matches_oracle(S, orc, solver):
     """Per-neuron replay over the whole 4000-step run of the 16384-neuron
     network: the GPU runs the full network (bench.py's configuration for
@@ -274,7 +282,7 @@ def test_full_length_replay_matches_oracle(S, orc, solver):
                                         [int(np.argmax(prob["n_comp"])),
                                          int(np.argmin(prob["n_comp"]))]]))
     say(f"case full cfg3 replay solver={solver} steps={steps} targets={len(targets)}")
-    with S.Simulation(prob, solver=solver, autotune=(solver == 1)) as g:
+    with S.Simulation(prob, solver=solver, autotune=(solver != 0)) as g:
         say("  config:", g.config)
         g.step(steps)
         v, s = g.voltages(), g.spikes()
@@ -291,3 +299,31 @@ def test_full_length_replay_matches_oracle(S, orc, solver):
     orc_sp = np.array(sorted(map(tuple, sr.tolist())), np.int64).reshape(-1, 2)
     compare(f"replay solver={solver}", want, vr, gpu_sp, orc_sp, tol(1, solver))
     assert len(s) > 10000 and len(orc_sp) > 50
+
+
+@pytest.mark.parametrize("solver", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("which", ["cfg1", "mini"])
+def test_backward_euler_axial_term_matches_oracle(S, orc, which, precision, solver):
+    """theta = 1 (backward Euler on the axial term instead of the factor 2 of
+    Eq. 2's Crank-Nicolson form): the off-diagonal becomes -G and no explicit
+    axial current enters the right-hand side; both sides take the same
+    reading."""
+    prob = W.config1() if which == "cfg1" else W.mini(seed=37, n_steps=240)
+    prob["params"]["theta"] = 1.0
+    steps = 400 if which == "cfg1" else 240
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, steps, precision, solver=solver)
+    compare(f"{which} theta=1 prec={precision} solver={solver}", v, vr, s, sr,
+            tol(precision, solver))
+    assert len(sr) > 0
+
+
+@pytest.mark.parametrize("solver", [0, 1, 2])
+def test_high_fanout_neurons_match_oracle(S, orc, solver):
+    """Somata with 64 unbranched children (and others with 5): a node of very
+    high fan-out, where the fast solver merges many child states into one
+    tip; every voltage and spike against the oracle."""
+    prob = W.star_network(n_steps=200)
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 200, 1, solver=solver)
+    compare(f"star fan-out 64 solver={solver}", v, vr, s, sr, tol(1, solver))
+    assert np.all(np.isfinite(v))

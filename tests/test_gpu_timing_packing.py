@@ -49,11 +49,14 @@ def test_launch_timing_counts_epochs_and_changes_nothing(S):
     assert launches == 4
     assert ms > 0
     for c in range(3):
-        c_ms, c_n, c_comps = cls[c]
+        c_ms, c_n, c_comps, c_upd = cls[c]
         if wg[c] == 0:
-            assert c_n == 0
+            assert c_n == 0 and c_upd == 0
             continue
         assert c_n == 4 and c_comps > 0
+        # the units of the timed launches: the class's compartments times the
+        # steps each launch ran (three whole epochs and a partial one)
+        assert c_upd == c_comps * steps
         assert 0 < c_ms <= ms * 1.02  # each launch lies inside its epoch
     with S.Simulation(prob, solver=1) as g:
         g.step(E + steps)

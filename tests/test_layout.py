@@ -1,0 +1,267 @@
+"""Host layout on the CPU (no GPU): sim_plan_create lays a problem out exactly
+as sim_create would for a given LDS size and CU count, without a device.
+
+- every neuron sits in exactly one pack, every pack in exactly one workgroup
+  list of one size class;
+- LDS accounting: each pack's table and state bytes equal the carve-up the
+  epoch kernel makes (restated here from the kernel's layout), LDS packs fit
+  their class's allocation, and a class allocates what its largest pack needs;
+- persistent scheduling is Graham's LPT list schedule: its makespan is at most
+  (4/3 - 1/(3m)) times the optimum, checked against brute force on up to 10
+  packs (P15);
+- the contraction solver's elimination schedule eliminates every compartment
+  once, each round's compartments are at distance >= 3 in the contracted
+  tree and have degree <= 2, and executing it solves the tree system (checked
+  against a dense solve).
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2005_06332_amd import workload as W
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2005_06332_amd import sim
+    sim.lib()
+    return sim
+
+
+def plan(S, prob, lds=160 * 1024, n_cu=256, **kw):
+    return S.Simulation(prob, plan=(lds, n_cu), **kw)
+
+
+def align(x, a):
+    return (x + a - 1) // a * a
+
+
+def table_bytes(info, tsize):
+    """Tables as the kernel carves them: branch records (16 B), synapse
+    weights, level offsets (4 B, 4-aligned), forward order and child list
+    (2 B each), synapse targets and run lengths (2 B each); then, for the
+    contraction solver, items (8 B per compartment, 8-aligned) and round
+    offsets (4 B); the whole rounded to 16 B."""
+    b = 16 * info["n_branches"] + tsize * info["n_syn"]
+    b = align(b, 4) + 4 * info["n_levels"]
+    b += 2 * info["n_branches"] + 2 * info["n_child_entries"] + 4 * info["n_syn"]
+    if info["n_rounds"] > 0:
+        b = align(b, 8) + 8 * info["n_comp"] + 4 * (info["n_rounds"] + 1)
+    return align(b, 16)
+
+
+def state_bytes(info, tsize):
+    """V, R, D and the off-diagonal (8 B per compartment each), synapse event
+    masks (8 B), spike masks and detector voltages (8 B per neuron each),
+    synaptic conductances (16-aligned), 64 B of sweep slack."""
+    n, s, k = info["n_comp"], info["n_syn"], info["n_neurons"]
+    return 32 * n + 8 * s + 16 * k + align(tsize * s, 16) + 64
+
+
+CASES = [
+    ("mini count", lambda: W.mini(), dict()),
+    ("mini plain", lambda: W.mini(), dict(packing=0)),
+    ("mini contract", lambda: W.mini(), dict(solver=2)),
+    ("mini fp64 small lds", lambda: W.mini(precision=0), dict(lds_comps=120, solver=2)),
+    ("cfg3 subset persistent", lambda: W.subset(W.make(3), np.arange(3000)),
+     dict(sched=1, lds_classes=3)),
+    ("cfg1 contract", lambda: W.config1(), dict(solver=2, sched=1)),
+]
+
+
+@pytest.mark.parametrize("name,mk,kw", CASES, ids=[c[0] for c in CASES])
+def test_layout_places_every_neuron_once_and_fits_lds(S, name, mk, kw):
+    prob = mk()
+    N = prob["n_comp"].shape[0]
+    tsize = 4 if prob["params"]["precision"] == 1 and kw.get("precision", 1) == 1 else 8
+    lds = 160 * 1024
+    with plan(S, prob, lds=lds, **kw) as g:
+        npk = g.pack_count()
+        seen = np.zeros(N, np.int64)
+        infos = []
+        for p in range(npk):
+            info = g.pack_info(p)
+            infos.append(info)
+            ids = g.pack_neurons(p)
+            seen[ids] += 1
+            assert info["n_comp"] == int(prob["n_comp"][ids].sum())
+            assert info["table_bytes"] == table_bytes(info, tsize), (name, p, info)
+            assert info["state_bytes"] == state_bytes(info, tsize), (name, p, info)
+        assert np.all(seen == 1)
+        ran = np.zeros(npk, np.int64)
+        for c in range(3):
+            n_wg, threads, cls_lds = g.class_launch(c)
+            assert cls_lds <= lds
+            need = 256
+            for w in range(n_wg):
+                for p in g.workgroup_packs(c, w):
+                    ran[p] += 1
+                    info = infos[p]
+                    assert info["size_class"] == c
+                    b = info["table_bytes"] + (0 if info["in_global"] else info["state_bytes"])
+                    assert b <= cls_lds
+                    need = max(need, b)
+            if n_wg:
+                assert need == cls_lds
+        assert np.all(ran == 1)
+
+
+def test_plan_refuses_what_needs_the_device(S):
+    prob = W.mini()
+    with pytest.raises(S.SimError):
+        plan(S, prob, autotune=True)
+    with plan(S, prob) as g:
+        with pytest.raises(S.SimError) as e:
+            g.step(1)
+        assert e.value.code == S.SIM_ESTATE
+        with pytest.raises(S.SimError):
+            g.voltages()
+
+
+def opt_makespan(costs, m):
+    """Minimum over all assignments of the largest machine load (branch and
+    bound over the items in decreasing order)."""
+    costs = sorted(costs, reverse=True)
+    best = [sum(costs)]
+    loads = [0.0] * m
+
+    def rec(i):
+        if i == len(costs):
+            best[0] = min(best[0], max(loads))
+            return
+        seen = set()
+        for w in range(m):
+            if loads[w] in seen or loads[w] + costs[i] >= best[0]:
+                continue
+            seen.add(loads[w])
+            loads[w] += costs[i]
+            rec(i + 1)
+            loads[w] -= costs[i]
+    rec(0)
+    return best[0]
+
+
+@pytest.mark.parametrize("seed,n,threads,lds", [
+    (41, 10, 1024, 64 * 1024), (42, 9, 640, 64 * 1024), (43, 10, 512, 160 * 1024),
+    (44, 8, 640, 64 * 1024), (45, 10, 1024, 64 * 1024), (46, 7, 512, 160 * 1024),
+])
+def test_persistent_schedule_is_within_graham_lpt_bound(S, seed, n, threads, lds):
+    """P15: one neuron per pack (pack_comps = 1), one CU, so the class-0
+    launch has m = 2..4 persistent workgroups; the static lists must be
+    Graham's LPT schedule, whose makespan is at most (4/3 - 1/(3m)) OPT."""
+    prob = W.mini(seed=seed, n_neurons=n, median=60)
+    with plan(S, prob, lds=lds, n_cu=1, sched=1, pack_comps=1, threads=threads) as g:
+        n_wg, _, _ = g.class_launch(0)
+        assert g.class_launch(1)[0] == 0
+        costs = [g.pack_info(p)["cost"] for p in range(g.pack_count())]
+        assert len(costs) == n
+        loads = [sum(costs[p] for p in g.workgroup_packs(0, w)) for w in range(n_wg)]
+    m = n_wg
+    assert 2 <= m <= 4
+    lpt = max(loads)
+    opt = opt_makespan(costs, m)
+    assert lpt <= (4.0 / 3.0 - 1.0 / (3 * m)) * opt + 1e-9, (lpt, opt, m)
+    # and it is the list schedule: packs by decreasing cost, each to the
+    # least loaded workgroup (ties to the lowest index)
+    order = sorted(range(n), key=lambda p: -costs[p])
+    sim_loads = [0.0] * m
+    for p in order:
+        w = min(range(m), key=lambda w: (sim_loads[w], w))
+        sim_loads[w] += costs[p]
+    assert sorted(sim_loads) == sorted(loads)
+
+
+def contracted_neighbours(parent_cur, children_cur, k):
+    nb = set(children_cur[k])
+    if parent_cur[k] >= 0:
+        nb.add(parent_cur[k])
+    return nb
+
+
+def execute_schedule(items, ro, p, e, d, r):
+    """The elimination the schedule describes, in numpy (test-side), then back
+    substitution in reverse round order."""
+    n = len(p)
+    D, R, V, EW = d.copy(), r.copy(), np.zeros(n), e.copy()
+    for q in range(len(items)):
+        k, n1, n2, up = items[q]
+        y = 1.0 / D[k]
+        a1 = (EW[k] if up else EW[n1]) if n1 >= 0 else 0.0
+        a2 = EW[n2] if n2 >= 0 else 0.0
+        if n1 >= 0:
+            D[n1] -= a1 * a1 * y
+            R[n1] -= a1 * R[k] * y
+        if n2 >= 0:
+            D[n2] -= a2 * a2 * y
+            R[n2] -= a2 * R[k] * y
+            if n1 >= 0:
+                EW[n2] = -a1 * a2 * y
+        R[k], EW[k], V[k] = R[k] * y, a1 * y, a2 * y
+    for rr in range(len(ro) - 2, -1, -1):
+        for q in range(ro[rr], ro[rr + 1]):
+            k, n1, n2, _ = items[q]
+            x = R[k]
+            if n1 >= 0:
+                x -= EW[k] * V[n1]
+            if n2 >= 0:
+                x -= V[k] * V[n2]
+            V[k] = x
+    return V
+
+
+@pytest.mark.parametrize("which", ["mini", "cfg1", "star", "cfg3"])
+def test_contraction_schedule_is_a_valid_elimination(S, which):
+    prob = {"mini": lambda: W.mini(), "cfg1": W.config1, "star": W.star_network,
+            "cfg3": lambda: W.subset(W.make(3), np.arange(24))}[which]()
+    rng = np.random.default_rng(5)
+    off = prob["comp_off"]
+    with plan(S, prob, solver=2) as g:
+        for j in range(min(prob["n_comp"].shape[0], 12)):
+            p = prob["parent"][off[j]:off[j + 1]].astype(np.int64)
+            n = p.shape[0]
+            items, ro = g.contraction_schedule(j, n)
+            assert sorted(items[:, 0].tolist()) == list(range(n))
+            assert ro[0] == 0 and ro[-1] == n and np.all(np.diff(ro) > 0)
+            # replay the contraction on the tree and check each round
+            par = p.copy()
+            ch = [set() for _ in range(n)]
+            for i in range(1, n):
+                ch[p[i]].add(i)
+            for rr in range(len(ro) - 1):
+                closed = set()
+                for q in range(ro[rr], ro[rr + 1]):
+                    k, n1, n2, up = (int(x) for x in items[q])
+                    nb = contracted_neighbours(par, ch, k)
+                    assert len(nb) <= 2
+                    assert nb == {x for x in (n1, n2) if x >= 0}
+                    assert (up == 1) == (n1 >= 0 and par[k] == n1)
+                    ball = nb | {k}
+                    assert not (ball & closed), "round members closer than 3"
+                    closed |= ball
+                for q in range(ro[rr], ro[rr + 1]):
+                    k, n1, n2, up = (int(x) for x in items[q])
+                    if par[k] >= 0:
+                        ch[par[k]].discard(k)
+                    for c in list(ch[k]):
+                        par[c] = -1
+                    if n1 >= 0 and n2 >= 0:  # n2 hangs off n1 from now on
+                        par[n2] = n1
+                        ch[n1].add(n2)
+                    ch[k] = set()
+                    par[k] = -2
+            # the elimination solves a random symmetric diagonally dominant
+            # system on this tree
+            e = np.zeros(n)
+            e[1:] = -rng.uniform(0.05, 1.0, n - 1)
+            dd = np.zeros(n)
+            np.add.at(dd, np.arange(1, n), -e[1:])
+            np.add.at(dd, p[1:], -e[1:])
+            d = dd + rng.uniform(0.2, 1.5, n)
+            rhs = rng.normal(size=n)
+            A = np.diag(d)
+            A[np.arange(1, n), p[1:]] = e[1:]
+            A[p[1:], np.arange(1, n)] = e[1:]
+            x = execute_schedule(items, ro, p, e, d, rhs)
+            ref = np.linalg.solve(A, rhs)
+            assert np.max(np.abs(x - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))

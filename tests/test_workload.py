@@ -113,3 +113,32 @@ def test_subset_keeps_only_synapses_among_the_kept_neurons():
     assert np.array_equal(sub["n_comp"], prob["n_comp"][keep])
     kept = np.isin(prob["syn_pre"], keep) & np.isin(prob["syn_post"], keep)
     assert sub["syn_pre"].shape[0] == int(kept.sum())
+
+
+def test_size_group_matches_the_section4_recipe():
+    """The Section-4 group: 20 sizes, spread exactly 700, mean exactly 300,
+    smallest at least 12; the multi-morphology network holds equally many
+    copies of each member, so it has exactly the mono network's
+    compartments."""
+    for seed in range(7, 17):
+        g = W.group_sizes(np.random.default_rng(seed))
+        assert g.shape == (20,)
+        assert g.max() - g.min() == 700
+        assert g.sum() == 20 * 300
+        assert g.min() >= 12
+    multi = W.size_group(7, 2000)
+    mono = W.size_group(7, 2000, mono=True)
+    assert multi["comp_off"][-1] == mono["comp_off"][-1] == 2000 * 300
+    sizes, counts = np.unique(multi["n_comp"], return_counts=True)
+    assert sizes.max() - sizes.min() == 700
+    assert abs(multi["n_comp"].mean() - 300.0) < 1e-12
+    assert set(mono["n_comp"].tolist()) == {300}
+
+
+def test_star_network_has_high_fanout_somata():
+    prob = W.star_network()
+    off = prob["comp_off"]
+    for j in range(prob["n_comp"].shape[0]):
+        p = prob["parent"][off[j]:off[j + 1]]
+        assert p[0] == -1 and np.all(p[1:] < np.arange(1, p.shape[0]))
+        assert int(np.sum(p == 0)) in (64, 5)
