@@ -184,7 +184,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
                     help="override the workload's precision (fp32 = FP32 gating, FP64 Hines)")
     ap.add_argument("--packing", default="count", choices=["plain", "count", "learned"])
-    ap.add_argument("--solver", default="fast", choices=["exact", "fast", "contract"],
+    ap.add_argument("--solver", default="contract", choices=["exact", "fast", "contract"],
                     help="exact: the elimination in the reference operation order (bitwise "
                          "equal to the CPU oracle); fast: division-free homogeneous form; "
                          "contract: tree contraction")

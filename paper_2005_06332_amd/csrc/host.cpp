@@ -283,6 +283,7 @@ struct Variant {
     int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
     int nclass = 2;  // LDS size classes in use (1..kClasses)
     int cls_thr = 1;  // class c launches threads << (c * cls_thr) (at most the launch bound)
+
 };
 
 template <typename X>
@@ -395,6 +396,7 @@ struct sim {
     } drain[2];
     int drain_slot = 0;
     std::vector<sim_spike_t> spikes;      // sorted by (step, neuron)
+
     std::vector<std::vector<int32_t>> by_t;  // scan scratch, one list per epoch step
 
     // time
@@ -1511,7 +1513,7 @@ void autotune(sim_t *s, Variant base) {
     // workgroups resident per CU, which hides the latency of the sweeps
     static const int kShapes[][2] = {{600, 800}, {800, 1100}, {1000, 1300}, {1400, 1800}};
     std::vector<Variant> cand;
-    for (int thr : {128, 256})
+    for (int thr : {128, 256, 320})
         for (const auto &sh : kShapes) {
             Variant v = base;
             v.threads = thr;
@@ -1524,6 +1526,23 @@ void autotune(sim_t *s, Variant base) {
         Variant v = base;
         v.sched = SIM_SCHED_DISPATCH;
         v.nclass = nc;
+        cand.push_back(v);
+    }
+    // the balance between the concurrent size classes: larger budgets for
+    // the small-pack class, and more threads for the larger-pack classes
+    for (int comps : {1500, 2000})
+        for (int nc : {2, 3}) {
+            Variant v = base;
+            v.sched = SIM_SCHED_DISPATCH;
+            v.lds_limit = lds_for(s, comps);
+            v.nclass = nc;
+            cand.push_back(v);
+        }
+    for (int nc : {2, 3}) {
+        Variant v = base;
+        v.sched = SIM_SCHED_DISPATCH;
+        v.nclass = nc;
+        v.cls_thr = 2;
         cand.push_back(v);
     }
     {

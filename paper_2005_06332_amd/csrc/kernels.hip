@@ -29,15 +29,17 @@
 
 namespace mmh {
 
+
 #ifdef MMH_PHASE_PROFILE
 // Optional per-phase wall-clock accounting (workgroup time in each phase of
-// the step loop), compiled only into profiling builds.
+// the step loop), compiled only into profiling builds: thread 0 sums each
+// phase's time in registers and adds the sums once per pack.
 __device__ unsigned long long g_phase_ticks[8];
 #define MMH_PHASE(k)                                                             \
     do {                                                                         \
         if (threadIdx.x == 0) {                                                  \
             const uint64_t now_ = wall_clock64();                                \
-            atomicAdd(&g_phase_ticks[k], (unsigned long long)(now_ - ph_t_));    \
+            ph_acc_[k] += now_ - ph_t_;                                          \
             ph_t_ = now_;                                                        \
         }                                                                        \
     } while (0)
@@ -548,21 +550,21 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // current neighbours n1, n2 (couplings a1, a2) is one step of Gaussian
 // elimination: each neighbour's diagonal loses a^2/d_k and its right-hand
 // side a r_k/d_k; when both exist, n2 is linked to n1 with the coupling
-// -a1 a2/d_k. Every compartment keeps in EW the coupling to its current
-// parent; the couplings of k needed later are g1 = a1/d_k (into EW[k]) and
-// g2 = a2/d_k (into V[k], free during the solve), with h = r_k/d_k into
-// R[k]. A round's eliminations are at least three apart in the current
+// -a1 a2/d_k. The V slot, free once the matrix is assembled, holds every
+// compartment's coupling to its current parent (W, a copy of the
+// off-diagonal at first). What k's back substitution needs replaces what k no
+// longer needs: h = r_k/d_k into R[k], g1 = a1/d_k into W[k], g2 = a2/d_k
+// into D[k]. A round's eliminations are at least three apart in the current
 // tree, so each survivor is written by one lane at most.
 __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
-                                              double *__restrict__ V, double *__restrict__ EW,
-                                              const uint64_t it) {
+                                              double *__restrict__ W, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
     const bool up = (it >> 15) & 1u;
     const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
     const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
     const double y = rcp_nr(D[k]);
-    const double a1 = h1 ? EW[up ? k : (int)n1] : 0.0;
-    const double a2 = h2 ? EW[n2] : 0.0;
+    const double a1 = h1 ? W[up ? k : (int)n1] : 0.0;
+    const double a2 = h2 ? W[n2] : 0.0;
     const double h = R[k] * y, g1 = a1 * y, g2 = a2 * y;
     if (h1) {
         D[n1] = __builtin_fma(-a1, g1, D[n1]);
@@ -571,23 +573,23 @@ __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__
     if (h2) {
         D[n2] = __builtin_fma(-a2, g2, D[n2]);
         R[n2] = __builtin_fma(-a2, h, R[n2]);
-        if (h1) EW[n2] = -(a1 * g2);
+        if (h1) W[n2] = -(a1 * g2);
     }
     R[k] = h;
-    EW[k] = g1;
-    V[k] = g2;
+    W[k] = g1;
+    D[k] = g2;
 }
 
-// Back substitution of k, its neighbours at elimination time solved already:
-// x_k = h - g1 x_n1 - g2 x_n2.
+// Back substitution of k, its neighbours at elimination time solved already
+// (their solutions in the V slot): x_k = h - g1 x_n1 - g2 x_n2, into V[k].
 __device__ __forceinline__ void contract_subst(const double *__restrict__ R,
-                                               double *__restrict__ V,
-                                               const double *__restrict__ EW, const uint64_t it) {
+                                               const double *__restrict__ D,
+                                               double *__restrict__ V, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
     const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
     double x = R[k];
-    if (n1 != kNoNb) x = __builtin_fma(-EW[k], V[n1], x);
-    if (n2 != kNoNb) x = __builtin_fma(-V[k], V[n2], x);
+    if (n1 != kNoNb) x = __builtin_fma(-V[k], V[n1], x);
+    if (n2 != kNoNb) x = __builtin_fma(-D[k], V[n2], x);
     V[k] = x;
 }
 
@@ -717,6 +719,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const Tables<T> tb = carve_tables<T>(smem, pk);
 #ifdef MMH_PHASE_PROFILE
     uint64_t ph_t_ = threadIdx.x == 0 ? wall_clock64() : 0;
+    uint64_t ph_acc_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #endif
     {
         const Branch *gbr = a.br + pk.br0;
@@ -764,14 +767,10 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const Consts cs{a.omt, a.v_thresh, a.ginv};
     const int t0 = a.t0, t1 = a.t1;
 
-    // the contraction solver keeps the working couplings in the Eo slot and
-    // reads the constant off-diagonal from global memory
-    const double *Ec = kContract ? a.e + c0 : Eo;
-
     // ---- load state -------------------------------------------------------
     for (int i = tid; i < n; i += NT) {
         V[i] = a.V[c0 + i];
-        if constexpr (!kContract) Eo[i] = a.e[c0 + i];
+        Eo[i] = a.e[c0 + i];
         R[i] = 0.0;  // synaptic conductance of compartment i in phases A/B
     }
     for (int k = tid; k < ns; k += NT) {
@@ -806,28 +805,31 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 
         // ---- B: membrane terms and assembly --------------------------------
 #pragma unroll 2
-        for (int i = tid; i < n; i += NT) {
-            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Ec, br, chl, niext,
+        for (int i = tid; i < n; i += NT)
+            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl, niext,
                         pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
-            if constexpr (kContract) Eo[i] = Ec[i];
-        }
         __syncthreads();
         MMH_PHASE(2);
 
         if constexpr (kContract) {
             // ---- C': contraction rounds, then back substitution ------------
-            // (V^n is no longer needed: detection keeps its own copy)
+            // (V^n is no longer needed: detection keeps its own copy, so the
+            // V slot takes the working couplings)
+            for (int i = tid; i < n; i += NT) V[i] = Eo[i];
+            __syncthreads();
+            // every thread takes items of each round, a workgroup barrier
+            // between rounds
             const uint64_t *cit = tb.cit;
             const int32_t *rof = tb.crof;
             for (int r = 0; r < pk.nrnd; ++r) {
                 for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
-                    contract_elim(D, R, V, Eo, cit[q2]);
+                    contract_elim(D, R, V, cit[q2]);
                 __syncthreads();
             }
             MMH_PHASE(3);
             for (int r = pk.nrnd - 1; r >= 0; --r) {
                 for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
-                    contract_subst(R, V, Eo, cit[q2]);
+                    contract_subst(R, D, V, cit[q2]);
                 __syncthreads();
             }
             MMH_PHASE(4);
@@ -922,6 +924,10 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             *w = *w | st.SP[k];
     }
     MMH_PHASE(6);
+#ifdef MMH_PHASE_PROFILE
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 7; ++k) atomicAdd(&g_phase_ticks[k], (unsigned long long)ph_acc_[k]);
+#endif
 }
 
 template <typename T, int kSolve>

@@ -203,7 +203,7 @@ def test_validation_errors_do_not_touch_the_device(S):
         S.Simulation(prob, epoch_steps=41)
     assert e.value.code == S.SIM_EINVAL
     with pytest.raises(S.SimError) as e:
-        S.Simulation(prob, solver=2)
+        S.Simulation(prob, solver=3)
     assert e.value.code == S.SIM_EINVAL
 
 
