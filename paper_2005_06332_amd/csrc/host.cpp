@@ -1423,7 +1423,9 @@ void advance(sim_t *s, int64_t n) {
         if (full > 0 && s->P.use_graph) {
             if (!s->exec1) capture(s, 1, s->graph1, s->exec1);
             if (!s->execK) capture(s, s->graphK_epochs, s->graphK, s->execK);
-            HIPCHK(hipMemcpy(s->d_epoch.p, &ep, sizeof(int64_t), hipMemcpyHostToDevice));
+            // stream-ordered: the replays of an earlier stretch may still be
+            // running on this stream and advancing the counter
+            HIPCHK(launch_fill_u64((uint64_t *)s->d_epoch.p, 1, (uint64_t)ep, s->stream));
             auto replay = [&](hipGraphExec_t ex, int epochs) {
                 std::pair<hipEvent_t, hipEvent_t> ev{};
                 if (s->kt_on) {

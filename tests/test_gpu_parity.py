@@ -327,3 +327,28 @@ def test_high_fanout_neurons_match_oracle(S, orc, solver):
     (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 200, 1, solver=solver)
     compare(f"star fan-out 64 solver={solver}", v, vr, s, sr, tol(1, solver))
     assert np.all(np.isfinite(v))
+
+
+@pytest.mark.parametrize("solver", [0, 1, 2])
+def test_one_long_call_equals_chunked_calls_and_oracle(S, orc, solver):
+    """One sim_step call long enough to wrap the spike ring several times (it
+    advances in stretches of at most 32 epochs, each replaying captured
+    graphs behind the previous one on the same stream) against the same
+    steps in short calls, bitwise, and against the oracle. A stretch sets the
+    device epoch counter in stream order; set out of order, the still-running
+    replays of the previous stretch would read the wrong history rows."""
+    prob = W.mini(seed=41, n_steps=2700, n_neurons=48)
+    steps = 2700
+    with S.Simulation(prob, solver=solver) as g:
+        g.step(steps)
+        v1, s1 = g.voltages(), g.spikes()
+    with S.Simulation(prob, solver=solver) as g:
+        for c in (500, 500, 500, 500, 500, 200):
+            g.step(c)
+        v2, s2 = g.voltages(), g.spikes()
+    assert np.array_equal(v1, v2) and np.array_equal(s1, s2)
+    ref = orc.Sim(prob, max_steps=steps)
+    ref.step(steps)
+    vr, sr = ref.voltages(), ref.spikes()
+    ref.close()
+    compare(f"mini one call of {steps} steps solver={solver}", v1, vr, s1, sr, tol(1, solver))
