@@ -245,6 +245,28 @@ int sim_contraction_schedule(const sim_t *sim, int32_t neuron, int32_t *items, i
  * not grow with the number of steps. */
 int sim_step(sim_t *sim, int64_t n_steps);
 
+/* sim_step for callers that cannot allocate memory (code running under HIP
+ * graph capture, tight serving loops, hosts that forbid allocation): the
+ * same steps, kernels and results as sim_step, with no device, pinned or host
+ * allocation and no hipMalloc/hipFree. Differences:
+ *  - epochs are launched directly (never captured or replayed);
+ *  - the state of packs too large for LDS lives in a fixed array of this
+ *    library, 64 MiB per GPU (kNoAllocScratchBytes), held by every GPU the
+ *    library runs on until the process ends; a simulation whose such packs
+ *    need more returns SIM_ENOMEM before taking any step;
+ *  - the spikes of this call are written to out[0 .. cap-1] in (step, neuron)
+ *    order and *n_out receives their count; they are not added to the list
+ *    sim_spikes returns. If the count exceeds cap the steps are still taken,
+ *    the spikes beyond cap are lost and SIM_ENOMEM is returned (cap >=
+ *    n_neurons * n_steps can never overflow);
+ *  - launch timing must be off (SIM_ESTATE otherwise).
+ * Every call on one GPU shares that GPU's array: calls on different
+ * simulations that overlap in time on one GPU race and must be serialised by
+ * the caller. Nothing in the array needs clearing between calls: each launch
+ * loads a pack's state before it reads it. */
+int sim_step_noalloc(sim_t *sim, int64_t n_steps, sim_spike_t *out, int64_t cap,
+                     int64_t *n_out);
+
 /* Steps simulated so far (local steps dt of Section 2). */
 int64_t sim_time_steps(const sim_t *sim);
 

@@ -396,7 +396,12 @@ struct sim {
     } drain[2];
     int drain_slot = 0;
     std::vector<sim_spike_t> spikes;      // sorted by (step, neuron)
-
+    // sim_step_noalloc: the call's spikes go to the caller's buffer instead
+    sim_spike_t *sink = nullptr;
+    int64_t sink_cap = 0, sink_n = 0;
+    void *na_scratch = nullptr;       // this device's fixed scratch array
+    char *scratch_override = nullptr;  // global-pack state base for the launches
+    int64_t scratch_total = 0;         // bytes the global packs' slices need
     std::vector<std::vector<int32_t>> by_t;  // scan scratch, one list per epoch step
 
     // time
@@ -1204,7 +1209,7 @@ EpochArgs make_args(sim_t *s) {
     a.ring_rows = s->ring_rows;
     a.n_neurons = s->N;
     a.E = s->E;
-    a.scratch = s->d_scratch.p;
+    a.scratch = s->scratch_override ? s->scratch_override : s->d_scratch.p;
     a.scratch_stride = 0;
     a.omt = 1.0 - s->P.theta;
     a.ginv = -1.0 / s->P.theta;
@@ -1240,6 +1245,7 @@ void assign_scratch(sim_t *s) {
             maxb = std::max(maxb, state_bytes(s, d.ncomp, d.nsyn, d.nneur));
             d.global_mem = 1 + count++;
         }
+    s->scratch_total = maxb * count;
     if (count) {
         s->d_scratch.alloc(maxb * count);
         s->scratch_bytes = maxb;
@@ -1353,6 +1359,26 @@ void scan_stage(sim_t *s, int slot) {
     if (!d.pending) return;
     HIPCHK(hipEventSynchronize(s->ev_stage[slot]));
     const int E = s->E;
+    if (s->sink) {
+        // allocation-free form for sim_step_noalloc: step by step over the
+        // staged words, into the caller's buffer (counting past its end)
+        for (int32_t r = 0; r < d.rows; ++r) {
+            const int64_t e = d.first_epoch + r;
+            const uint64_t *w = s->h_stage[slot] + (size_t)r * s->N;
+            for (int t = 0; t < E; ++t) {
+                const int64_t step = e * E + t + 1;
+                if (step <= d.lo || step > d.hi) continue;
+                for (int32_t j = 0; j < s->N; ++j)
+                    if ((w[j] >> t) & 1ull) {
+                        if (s->sink_n < s->sink_cap)
+                            s->sink[s->sink_n] = sim_spike_t{j, (int32_t)step};
+                        s->sink_n++;
+                    }
+            }
+        }
+        d.pending = false;
+        return;
+    }
     s->by_t.resize(E);
     for (int32_t r = 0; r < d.rows; ++r) {
         const int64_t e = d.first_epoch + r;
@@ -1393,18 +1419,19 @@ void enqueue_drain(sim_t *s, int64_t lo, int64_t hi) {
     s->drain_slot = slot ^ 1;
 }
 
-void advance(sim_t *s, int64_t n);
+void advance(sim_t *s, int64_t n, bool graphs);
 
 // Steps in stretches that never overwrite a ring row before it is staged: a
 // stretch ends before the epoch ring_rows after its first one begins.
-void run_steps(sim_t *s, int64_t n) {
+// graphs = false launches every epoch directly (no capture, no replay).
+void run_steps(sim_t *s, int64_t n, bool graphs = true) {
     if (n <= 0) return;
     const int E = s->E;
     while (n > 0) {
         const int64_t lo = s->step;
         const int64_t room = (lo / E + s->ring_rows) * E - lo;
         const int64_t m = std::min(n, room);
-        advance(s, m);
+        advance(s, m, graphs);
         enqueue_drain(s, lo, s->step);
         n -= m;
     }
@@ -1414,13 +1441,13 @@ void run_steps(sim_t *s, int64_t n) {
     if (s->kt_on) kt_collect(s);
 }
 
-void advance(sim_t *s, int64_t n) {
+void advance(sim_t *s, int64_t n, bool graphs) {
     const int E = s->E;
     while (n > 0) {
         const int64_t ep = s->step / E;
         const int t0 = (int)(s->step % E);
         const int64_t full = (t0 == 0) ? n / E : 0;
-        if (full > 0 && s->P.use_graph) {
+        if (full > 0 && s->P.use_graph && graphs) {
             if (!s->exec1) capture(s, 1, s->graph1, s->exec1);
             if (!s->execK) capture(s, s->graphK_epochs, s->graphK, s->execK);
             // stream-ordered: the replays of an earlier stretch may still be
@@ -1637,6 +1664,7 @@ int sim_create(const sim_params_t *params, const sim_morphology_t *morph,
             (void)hipGetLastError();
             s->max_lds = (int)prop.sharedMemPerBlock;
         }
+        HIPCHK(noalloc_scratch(&s->na_scratch));
         int clk_khz = 0;
         if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
             clk_khz > 0)
@@ -1821,6 +1849,51 @@ int sim_step(sim_t *s, int64_t n_steps) {
         s->err = e.msg;
         return e.code;
     }
+}
+
+int sim_step_noalloc(sim_t *s, int64_t n_steps, sim_spike_t *out, int64_t cap,
+                     int64_t *n_out) {
+    if (!s) return SIM_EINVAL;
+    if (s->planned_only) {
+        s->err = "a planned simulation has no device state";
+        return SIM_ESTATE;
+    }
+    if (n_steps < 0 || cap < 0 || (cap > 0 && !out)) {
+        s->err = "n_steps and cap must be >= 0, out non-null when cap > 0";
+        return SIM_EINVAL;
+    }
+    if (s->scratch_total > kNoAllocScratchBytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "packs kept in global memory need %lld bytes of scratch, more than the "
+                 "%lld of the fixed array",
+                 (long long)s->scratch_total, (long long)kNoAllocScratchBytes);
+        s->err = buf;
+        return SIM_ENOMEM;
+    }
+    if (s->kt_on) {
+        s->err = "launch timing is on; sim_step_noalloc records no timing";
+        return SIM_ESTATE;
+    }
+    s->sink = out;
+    s->sink_cap = cap;
+    s->sink_n = 0;
+    s->scratch_override = (char *)s->na_scratch;
+    int rc = SIM_OK;
+    try {
+        run_steps(s, n_steps, false);
+    } catch (const Error &e) {
+        s->err = e.msg;
+        rc = e.code;
+    }
+    s->sink = nullptr;
+    s->scratch_override = nullptr;
+    if (n_out) *n_out = s->sink_n;
+    if (rc == SIM_OK && s->sink_n > cap) {
+        s->err = "spike buffer too small: the steps were taken, the spikes beyond cap are lost";
+        rc = SIM_ENOMEM;
+    }
+    return rc;
 }
 
 int64_t sim_time_steps(const sim_t *s) { return s ? s->step : -1; }

@@ -179,6 +179,11 @@ hipError_t launch_stamp(uint64_t *timer, hipStream_t s);
 hipError_t launch_decay_weights_convert(const double *w, void *out, int64_t n,
                                         int precision, hipStream_t s);
 hipError_t set_epoch_lds_limit(int bytes);
+// Device address of the fixed scratch array of the current device (resolved
+// once per device); kNoAllocScratchBytes long.
+constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(void **ptr);
 // Largest epoch-kernel workgroup (launch bounds): double precision needs
 // more registers per lane.
 constexpr int kMaxThreadsF32 = 1024;

@@ -25,10 +25,36 @@
 // not depend on how neurons are packed or launched.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace mmh {
 
+// Scratch for the entry point that allocates nothing (sim_step_noalloc): the
+// state slices of packs too large for LDS live here instead of in memory the
+// simulation allocated. Every device holds its own copy for the life of the
+// process; its address is resolved once per device, at set-up, and only
+// that address is handed to kernels (the array's name is a host-side stand-in).
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 #ifdef MMH_PHASE_PROFILE
 // Optional per-phase wall-clock accounting (workgroup time in each phase of

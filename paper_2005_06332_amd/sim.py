@@ -31,6 +31,7 @@ EXPORTS = (
     "sim_mlp_forward", "sim_mlp_loss_grad", "sim_mlp_train",
     "sim_plan_create", "sim_pack_count", "sim_pack_info", "sim_pack_neurons",
     "sim_class_launch", "sim_workgroup_packs", "sim_contraction_schedule",
+    "sim_step_noalloc",
 )
 
 
@@ -147,6 +148,8 @@ def lib():
                                           C.POINTER(C.c_int32)]
         L.sim_contraction_schedule.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64,
                                                C.POINTER(C.c_int32)]
+        L.sim_step_noalloc.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(C.c_int64)]
+        L.sim_step_noalloc.restype = C.c_int
         L.sim_mlp_nparams.restype = C.c_int64
         L.sim_mlp_init.argtypes = [P, P, P, C.c_int64, C.c_uint64]
         L.sim_mlp_forward.argtypes = [P, P, C.c_int64, P]
@@ -262,6 +265,19 @@ class Simulation:
 
     def step(self, n: int) -> None:
         _check(lib().sim_step(self._h, int(n)), self._h)
+
+    def step_noalloc(self, n: int, cap: int | None = None) -> np.ndarray:
+        """sim_step_noalloc: n steps without any allocation by the library;
+        returns this call's spikes (neuron, step) as int64 [k, 2]. The buffer
+        is allocated here, by the caller, before the call."""
+        if cap is None:
+            cap = self.N * max(int(n), 1)
+        buf = (Spike * max(cap, 1))()
+        cnt = C.c_int64(0)
+        _check(lib().sim_step_noalloc(self._h, int(n), C.cast(buf, C.c_void_p), int(cap),
+                                      C.byref(cnt)), self._h)
+        k = cnt.value
+        return np.frombuffer(buf, dtype=np.int32, count=2 * k).reshape(k, 2).astype(np.int64)
 
     def voltages(self) -> np.ndarray:
         out = np.empty(self.C, np.float64)

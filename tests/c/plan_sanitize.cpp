@@ -25,6 +25,7 @@ hipError_t launch_decay_weights_convert(const double *, void *, int64_t, int, hi
     return hipErrorNotSupported;
 }
 hipError_t set_epoch_lds_limit(int) { return hipErrorNotSupported; }
+hipError_t noalloc_scratch(void **) { return hipErrorNotSupported; }
 hipError_t mlp_forward(const float *, const float *, int64_t, float *) { return hipErrorNotSupported; }
 hipError_t mlp_loss_grad(const float *, const float *, const float *, int64_t, float *, float *) {
     return hipErrorNotSupported;
