@@ -141,8 +141,8 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
 // Bytes of the pack's tables staged in LDS next to the state: branch records,
 // synapse weights (T), level offsets, the forward order, child list, synapse
 // targets and run lengths. Must match the carve-up in the kernel.
-// The contraction solver adds its items (8 B per compartment) and round
-// offsets (nrnd + 1 ints); nrnd = 0 for the other solvers.
+// The contraction solver adds its round offsets (nrnd + 1 ints; its items
+// stay in global memory); nrnd = 0 for the other solvers.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn, int64_t ncomp = 0,
@@ -151,7 +151,8 @@ __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, in
     b += (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
     b += 2 * nbr + 2 * nch + 2 * 2 * nsyn;
-    if (nrnd > 0) b = (b + 7) / 8 * 8 + 8 * ncomp + 4 * (nrnd + 1);
+    if (nrnd > 0) b = (b + 3) / 4 * 4 + 4 * (nrnd + 1);
+    (void)ncomp;
     return (b + 15) / 16 * 16;
 }
 

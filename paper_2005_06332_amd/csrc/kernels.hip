@@ -701,8 +701,7 @@ struct Tables {
     T *sw;
     int32_t *lvl;
     uint16_t *chl, *scomp, *sseg;
-    uint64_t *cit;  // contraction items, then round offsets
-    int32_t *crof;
+    int32_t *crof;  // contraction round offsets
 };
 
 template <typename T>
@@ -718,9 +717,7 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
     t.scomp = t.chl + pk.nch;
     t.sseg = t.scomp + pk.nsyn;
     char *q = (char *)(t.sseg + pk.nsyn);
-    q = smem + (((q - smem) + 7) / 8) * 8;
-    t.cit = (uint64_t *)q;
-    t.crof = (int32_t *)(t.cit + (pk.nrnd > 0 ? pk.ncomp : 0));
+    t.crof = (int32_t *)(smem + (((q - smem) + 3) / 4) * 4);
     return t;
 }
 
@@ -765,8 +762,6 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             tb.sseg[k] = a.sseg[s0 + k];
         }
         if constexpr (kContract) {
-            const uint64_t *gci = a.cit + pk.it0;
-            for (int k = tid; k < n; k += NT) tb.cit[k] = gci[k];
             const int32_t *gro = a.lvl + pk.lv0 + pk.nbw + pk.nfw + 2;
             for (int k = tid; k <= pk.nrnd; k += NT) tb.crof[k] = gro[k];
         }
@@ -844,19 +839,44 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             for (int i = tid; i < n; i += NT) V[i] = Eo[i];
             __syncthreads();
             // every thread takes items of each round, a workgroup barrier
-            // between rounds
-            const uint64_t *cit = tb.cit;
+            // between rounds; the items stay in global memory (L2), and each
+            // thread reads its first item of the next round before working on
+            // the current one, so the read overlaps the round and its barrier
+            const uint64_t *__restrict__ cit = a.cit + pk.it0;
             const int32_t *rof = tb.crof;
-            for (int r = 0; r < pk.nrnd; ++r) {
-                for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
-                    contract_elim(D, R, V, cit[q2]);
-                __syncthreads();
+            const int nr = pk.nrnd;
+            {
+                int lo = rof[0], hi = rof[nr > 0 ? 1 : 0];
+                uint64_t cur = (lo + tid < hi) ? cit[lo + tid] : 0ull;
+                for (int r = 0; r < nr; ++r) {
+                    // the next round's end and first item, read before this
+                    // round's work and barrier
+                    const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
+                    const uint64_t nxt = (hi + tid < hi2) ? cit[hi + tid] : 0ull;
+                    if (lo + tid < hi) contract_elim(D, R, V, cur);
+                    for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
+                        contract_elim(D, R, V, cit[q2]);
+                    __syncthreads();
+                    lo = hi;
+                    hi = hi2;
+                    cur = nxt;
+                }
             }
             MMH_PHASE(3);
-            for (int r = pk.nrnd - 1; r >= 0; --r) {
-                for (int q2 = rof[r] + tid; q2 < rof[r + 1]; q2 += NT)
-                    contract_subst(R, D, V, cit[q2]);
-                __syncthreads();
+            {
+                int hi = rof[nr], lo = rof[nr > 0 ? nr - 1 : 0];
+                uint64_t cur = (lo + tid < hi) ? cit[lo + tid] : 0ull;
+                for (int r = nr - 1; r >= 0; --r) {
+                    const int lo2 = (r > 0) ? rof[r - 1] : lo;
+                    const uint64_t nxt = (lo2 + tid < lo) ? cit[lo2 + tid] : 0ull;
+                    if (lo + tid < hi) contract_subst(R, D, V, cur);
+                    for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
+                        contract_subst(R, D, V, cit[q2]);
+                    __syncthreads();
+                    hi = lo;
+                    lo = lo2;
+                    cur = nxt;
+                }
             }
             MMH_PHASE(4);
         } else {

@@ -41,13 +41,13 @@ def table_bytes(info, tsize):
     """Tables as the kernel carves them: branch records (16 B), synapse
     weights, level offsets (4 B, 4-aligned), forward order and child list
     (2 B each), synapse targets and run lengths (2 B each); then, for the
-    contraction solver, items (8 B per compartment, 8-aligned) and round
-    offsets (4 B); the whole rounded to 16 B."""
+    contraction solver, round offsets (4 B; its items stay in global
+    memory); the whole rounded to 16 B."""
     b = 16 * info["n_branches"] + tsize * info["n_syn"]
     b = align(b, 4) + 4 * info["n_levels"]
     b += 2 * info["n_branches"] + 2 * info["n_child_entries"] + 4 * info["n_syn"]
     if info["n_rounds"] > 0:
-        b = align(b, 8) + 8 * info["n_comp"] + 4 * (info["n_rounds"] + 1)
+        b = align(b, 4) + 4 * (info["n_rounds"] + 1)
     return align(b, 16)
 
 
