@@ -66,10 +66,11 @@ def describe(prob: dict) -> str:
 
 
 def time_run(S, prob, steps, warmup, packing, cost_model=None, autotune=True, stream=None,
-             solver=1):
+             solver=1, lds_classes=0):
     import torch
     g = S.Simulation(prob, packing=packing, autotune=autotune, cost_model=cost_model,
-                     stream=stream.cuda_stream if stream is not None else None, solver=solver)
+                     stream=stream.cuda_stream if stream is not None else None, solver=solver,
+                     lds_classes=lds_classes)
     torch.cuda.synchronize()
     if warmup:
         g.step(warmup)
@@ -191,6 +192,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-packing comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--lds-classes", type=int, default=0,
+                    help="fix the number of LDS size classes (1..3) instead of autotuning the "
+                         "layout (the counter runs use it to reproduce the benchmarked layout)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed run, copy 1 GiB with a plain copy kernel (reference "
                          "for the HBM byte counters)")
@@ -220,7 +224,8 @@ def main():
 
     solver = dict(exact=S.SOLVE_EXACT, fast=S.SOLVE_FAST, contract=S.SOLVE_CONTRACT)[args.solver]
     g, ms = time_run(S, prob, args.steps, args.warmup, packing, cost_model,
-                     autotune=not args.no_autotune, stream=stream, solver=solver)
+                     autotune=not (args.no_autotune or args.lds_classes), stream=stream,
+                     solver=solver, lds_classes=args.lds_classes)
     config_str = g.config
     E = int(config_str.split("E=")[1].split()[0])
     # the dominant kernel: the launch of size class 0 (most packs), its
@@ -269,7 +274,7 @@ def main():
             rec = json.load(f)
         if (rec.get("kernel_source_sha1") == kernel_source_hash()
                 and abs(rec.get("steps_per_launch", -1) - steps_per_launch) < 1e-9
-                and rec.get("solver") == args.solver and rec.get("packing") == args.packing):
+                and rec.get("launch") == config_str):
             traffic = rec.get("bytes_per_launch")
 
     out = {
