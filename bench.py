@@ -219,10 +219,10 @@ def main():
 
     cost_model = None
     packing = dict(plain=S.PACK_PLAIN, count=S.PACK_COUNT, learned=S.PACK_LEARNED)[args.packing]
-    if packing == S.PACK_LEARNED:
-        cost_model = costmodel.load_or_train(prob)
-
     solver = dict(exact=S.SOLVE_EXACT, fast=S.SOLVE_FAST, contract=S.SOLVE_CONTRACT)[args.solver]
+    if packing == S.PACK_LEARNED:
+        cost_model = costmodel.load_or_train(prob, solver=solver)
+
     g, ms = time_run(S, prob, args.steps, args.warmup, packing, cost_model,
                      autotune=not (args.no_autotune or args.lds_classes), stream=stream,
                      solver=solver, lds_classes=args.lds_classes)

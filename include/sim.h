@@ -211,6 +211,14 @@ typedef struct {
     int64_t table_bytes;    /* LDS bytes of the pack's tables */
     int64_t state_bytes;    /* bytes of its state (LDS unless in_global) */
     double cost;            /* packing cost (compartments, or predicted time) */
+    int32_t n_wide_rounds;  /* contraction: leading rounds run by the whole
+                               workgroup; the later ones, at most 64 items
+                               each, by its first wavefront alone */
+    int32_t n_staged_items; /* contraction: the last items of the pack's
+                               schedule (the single-wavefront tail) copied
+                               to LDS, as many as the class's LDS budget
+                               leaves room for; the rest stay in global
+                               memory */
 } sim_pack_info_t;
 
 /* Number of packs (workgroup units of work). */

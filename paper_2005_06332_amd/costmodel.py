@@ -21,12 +21,15 @@ from . import sim as S
 from . import workload as W
 
 
-def calibrate(prob: dict, epochs: int = 2, threads: int = 256):
-    """Per-neuron kernel time (ns per epoch) with one neuron per pack.
+def calibrate(prob: dict, epochs: int = 2, threads: int = 256, solver: int = S.SOLVE_EXACT):
+    """Per-neuron kernel time (ns per epoch) with one neuron per pack, under
+    the tree solver the packing is for (a neuron's cost depends on it: serial
+    sweeps for the exact solver, level counts for the fast one, contraction
+    rounds for the contraction solver).
     Returns (features [N,16] float32, log time [N] float32)."""
     with S.Simulation(prob, packing=S.PACK_COUNT, sched=S.SCHED_PERSISTENT, pack_comps=1,
                       threads=threads, record_timings=True, autotune=False,
-                      use_graph=False) as g:
+                      use_graph=False, solver=solver) as g:
         E = int(g.config.split("E=")[1].split()[0])
         g.step(E)
         g.neuron_timings(reset=True)
@@ -54,17 +57,18 @@ def fit_quality(params: np.ndarray, features: np.ndarray, log_t: np.ndarray) -> 
 
 
 def load_or_train(prob_like: dict | None = None, n_neurons: int = 4096,
-                  cache_dir: str | None = None):
+                  cache_dir: str | None = None, solver: int = S.SOLVE_EXACT):
     """Parameters trained on a calibration run of the 16384-neuron
-    multi-morphology recipe (seed 3, first n_neurons neurons), cached."""
+    multi-morphology recipe (seed 3, first n_neurons neurons) under the given
+    tree solver, cached per solver."""
     cache_dir = cache_dir or os.environ.get("MMHINES_CACHE", "/tmp/mmhines_cache")
-    key = hashlib.sha1(repr(("cm", 3, n_neurons, 1)).encode()).hexdigest()[:12]
+    key = hashlib.sha1(repr(("cm", 3, n_neurons, 1, int(solver))).encode()).hexdigest()[:12]
     path = os.path.join(cache_dir, f"costmodel_{key}.npy")
     if os.path.exists(path):
         return np.load(path)
     calib = W.make(3)
     calib = W.subset(calib, np.arange(min(n_neurons, calib["n_comp"].shape[0])))
-    f, y = calibrate(calib)
+    f, y = calibrate(calib, solver=solver)
     p, _ = train(f, y)
     try:
         os.makedirs(cache_dir, exist_ok=True)

@@ -697,12 +697,19 @@ void build_layout(sim_t *s, Variant v) {
             int cls = 0;
             double cost = 0.0;
         };
+        // (contraction: room for the staged tail items, about one in
+        // kTailShare compartments)
+#ifndef MMH_TAIL_SHARE
+#define MMH_TAIL_SHARE 8
+#endif
+        const int64_t tail_share = MMH_TAIL_SHARE;
         auto bytes_of = [&](int64_t n, int64_t ns, int32_t nbr, int32_t nch, int32_t maxh,
                             int32_t maxd, int32_t maxr, int64_t k) -> int64_t {
             const int64_t nlev = (int64_t)maxh + maxd + 4;
-            return s->tsize == 8 ? pack_table_bytes<double>(nbr, nch, nlev, ns, n, maxr) +
+            const int64_t nst = (maxr > 0 && tail_share > 0) ? n / tail_share : 0;
+            return s->tsize == 8 ? pack_table_bytes<double>(nbr, nch, nlev, ns, n, maxr, nst) +
                                        pack_state_bytes<double>(n, ns, k)
-                                 : pack_table_bytes<float>(nbr, nch, nlev, ns, n, maxr) +
+                                 : pack_table_bytes<float>(nbr, nch, nlev, ns, n, maxr, nst) +
                                        pack_state_bytes<float>(n, ns, k);
         };
         std::vector<Bin> bins;
@@ -969,6 +976,8 @@ void build_layout(sim_t *s, Variant v) {
         d.nch = (int32_t)chl.size() - d.ch0;
         d.it0 = 0;
         d.nrnd = 0;
+        d.nrw = 0;
+        d.nst = 0;
         if (s->solver == SIM_SOLVE_CONTRACT) {
             // round r of the pack: round r of each of its neurons, in pack
             // order, renumbered pack-locally; offsets follow the levels
@@ -998,6 +1007,11 @@ void build_layout(sim_t *s, Variant v) {
             }
             if ((int64_t)cit.size() - d.it0 != d.ncomp)
                 throw fail(SIM_EINVAL, "internal: contraction schedule does not cover the pack");
+            // the tail of rounds that one wavefront can take: every round
+            // from nrw on has at most kWave items
+            const int32_t *ro = lvl.data() + (lvl.size() - (size_t)maxr - 1);
+            d.nrw = maxr;
+            while (d.nrw > 0 && ro[d.nrw] - ro[d.nrw - 1] <= kWave) --d.nrw;
             if (cit.size() > (size_t)INT32_MAX) throw fail(SIM_ENOMEM, "contraction table too large");
         }
         d.tbytes = (int32_t)(s->tsize == 8
@@ -1012,11 +1026,30 @@ void build_layout(sim_t *s, Variant v) {
         if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
         int c = 0;
         while (c + 1 < ncls && d.tbytes + bytes > cls_budget[c]) ++c;
-        if (d.tbytes + bytes <= cls_budget[c]) {
-            d.global_mem = 0;
+        d.global_mem = d.tbytes + bytes <= cls_budget[c] ? 0 : 1;
+        if (s->solver == SIM_SOLVE_CONTRACT && d.nrnd > 0) {
+            // stage the single-wavefront tail of the schedule in LDS, as much
+            // of it as the class budget leaves room for: those rounds are
+            // short, so an item read from global memory would stall each one
+            const int32_t *ro = lvl.data() + (lvl.size() - (size_t)d.nrnd - 1);
+            const int64_t in_lds = d.global_mem ? 0 : bytes;
+            auto tb_with = [&](int64_t nst) {
+                return s->tsize == 8 ? pack_table_bytes<double>(d.nbr, d.nch, d.nbw + d.nfw + 2,
+                                                                d.nsyn, d.ncomp, d.nrnd, nst)
+                                     : pack_table_bytes<float>(d.nbr, d.nch, d.nbw + d.nfw + 2,
+                                                               d.nsyn, d.ncomp, d.nrnd, nst);
+            };
+            int64_t nst = d.ncomp - ro[d.nrw];
+            const int64_t room = (cls_budget[c] - in_lds - d.tbytes) / 8 + 2;
+            nst = std::max<int64_t>(0, std::min(nst, room));
+            while (nst > 0 && tb_with(nst) + in_lds > std::max<int64_t>(cls_budget[c], d.tbytes))
+                --nst;
+            d.nst = (int32_t)nst;
+            d.tbytes = (int32_t)tb_with(nst);
+        }
+        if (!d.global_mem) {
             lds_cls[c] = std::max(lds_cls[c], d.tbytes + bytes);
         } else {
-            d.global_mem = 1;
             lds_cls[c] = std::max<int64_t>(lds_cls[c], d.tbytes);
             scratch = std::max(scratch, bytes);
         }
@@ -1777,6 +1810,8 @@ int sim_pack_info(const sim_t *s, int32_t pack, sim_pack_info_t *out) {
     out->table_bytes = d.tbytes;
     out->state_bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
     out->cost = s->pack_cost[pack];
+    out->n_wide_rounds = d.nrw;
+    out->n_staged_items = d.nst;
     return SIM_OK;
 }
 

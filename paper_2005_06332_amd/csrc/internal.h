@@ -57,7 +57,14 @@ struct PackDesc {
     int32_t nch;           // child list entries
     int32_t tbytes;        // bytes of staged tables (always in LDS)
     int32_t it0, nrnd;     // contraction solver: first item, rounds (0: other solvers)
+    int32_t nrw;           // contraction rounds [0, nrw) run by the whole workgroup,
+                           // rounds [nrw, nrnd) (at most kWave items each) by its
+                           // first wavefront alone, with no workgroup barrier
+    int32_t nst;           // contraction: the last nst items staged in LDS
 };
+
+// Lanes of a wavefront on gfx950.
+constexpr int kWave = 64;
 
 // Contraction solver item, one per compartment of a pack: bits 0..14 the
 // eliminated compartment k, bit 15 set when n1 is k's current parent, bits
@@ -146,12 +153,13 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn, int64_t ncomp = 0,
-                                                    int64_t nrnd = 0) {
+                                                    int64_t nrnd = 0, int64_t nst = 0) {
     int64_t b = (int64_t)sizeof(Branch) * nbr;
     b += (int64_t)sizeof(T) * nsyn;
     b = (b + 3) / 4 * 4 + 4 * nlev;
     b += 2 * nbr + 2 * nch + 2 * 2 * nsyn;
     if (nrnd > 0) b = (b + 3) / 4 * 4 + 4 * (nrnd + 1);
+    if (nst > 0) b = (b + 7) / 8 * 8 + 8 * nst;
     (void)ncomp;
     return (b + 15) / 16 * 16;
 }

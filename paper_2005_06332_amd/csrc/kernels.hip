@@ -582,25 +582,30 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // longer needs: h = r_k/d_k into R[k], g1 = a1/d_k into W[k], g2 = a2/d_k
 // into D[k]. A round's eliminations are at least three apart in the current
 // tree, so each survivor is written by one lane at most.
+// k, n1 and n2 are distinct, so every value is read before anything is
+// written, and with no branches: the reads go out together (one LDS round
+// trip) rather than each waiting for the write before it, as they would if
+// the compiler had to assume the slots may alias. An absent neighbour
+// stands in for k: its reads are k's values and its writes put them back
+// unchanged, before k's own results are written.
 __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
                                               double *__restrict__ W, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
     const bool up = (it >> 15) & 1u;
     const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
     const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
-    const double y = rcp_nr(D[k]);
-    const double a1 = h1 ? W[up ? k : (int)n1] : 0.0;
-    const double a2 = h2 ? W[n2] : 0.0;
-    const double h = R[k] * y, g1 = a1 * y, g2 = a2 * y;
-    if (h1) {
-        D[n1] = __builtin_fma(-a1, g1, D[n1]);
-        R[n1] = __builtin_fma(-a1, h, R[n1]);
-    }
-    if (h2) {
-        D[n2] = __builtin_fma(-a2, g2, D[n2]);
-        R[n2] = __builtin_fma(-a2, h, R[n2]);
-        if (h1) W[n2] = -(a1 * g2);
-    }
+    const int i1 = h1 ? (int)n1 : k, i2 = h2 ? (int)n2 : k;
+    const double dk = D[k], rk = R[k];
+    const double w1 = W[up ? k : i1], w2 = W[i2];
+    const double d1 = D[i1], r1 = R[i1], d2 = D[i2], r2 = R[i2];
+    const double a1 = h1 ? w1 : 0.0, a2 = h2 ? w2 : 0.0;
+    const double y = rcp_nr(dk);
+    const double h = rk * y, g1 = a1 * y, g2 = a2 * y;
+    D[i1] = h1 ? __builtin_fma(-a1, g1, d1) : d1;
+    R[i1] = h1 ? __builtin_fma(-a1, h, r1) : r1;
+    D[i2] = h2 ? __builtin_fma(-a2, g2, d2) : d2;
+    R[i2] = h2 ? __builtin_fma(-a2, h, r2) : r2;
+    W[i2] = (h1 && h2) ? -(a1 * g2) : w2;
     R[k] = h;
     W[k] = g1;
     D[k] = g2;
@@ -613,47 +618,75 @@ __device__ __forceinline__ void contract_subst(const double *__restrict__ R,
                                                double *__restrict__ V, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
     const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
-    double x = R[k];
-    if (n1 != kNoNb) x = __builtin_fma(-V[k], V[n1], x);
-    if (n2 != kNoNb) x = __builtin_fma(-D[k], V[n2], x);
+    const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
+    const double rk = R[k], g1 = V[k], g2 = D[k];
+    const double x1 = V[h1 ? (int)n1 : k], x2 = V[h2 ? (int)n2 : k];
+    double x = rk;
+    if (h1) x = __builtin_fma(-g1, x1, x);
+    if (h2) x = __builtin_fma(-g2, x2, x);
     V[k] = x;
+}
+
+// Makes this wavefront's LDS writes visible to all of its lanes: waits for
+// them to complete and keeps the compiler from moving LDS accesses across
+// (a workgroup-scope release/acquire pair without the workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 struct Consts {
     double omt, vth, ginv;
 };
 
-// Phase B for one compartment: membrane conductance and source from the gates
-// of step n, axial current and diagonal from the couplings to the parent and
-// the children (children in ascending order, as the time-invariant diagonal
-// is defined), then D_i and R_i.
+// Channel constants of the membrane model, in the gating precision.
+template <typename T>
+struct Chan {
+    T gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
+};
+
+// Membrane conductance and source of one compartment from its gates, per
+// unit of the compartment's own area factor: P = a*g_ion, Q = a*J_ion
+// (HH: g = gNa m^3 h + gK n^4 + gL, J = gNa m^3 h ENa + gK n^4 EK + gL EL;
+// passive: g_pas and g_pas e_pas). They are formed when the gates are
+// advanced, so that the assembly of the next step needs no gates; the
+// synaptic delivery then adds g_syn to P and g_syn E_syn to Q.
+template <typename T>
+__device__ __forceinline__ void membrane(const uint32_t tp, const T afv, const T m, const T h,
+                                         const T x, const Chan<T> &c, T &P, T &Q) {
+    T gion, jion;
+    if (topo_hh(tp)) {
+        const T gna = c.gnabar * (((m * m) * m) * h);
+        const T gk = c.gkbar * (((x * x) * x) * x);
+        gion = (gna + gk) + c.gl;
+        jion = (gna * c.ena + gk * c.ek) + c.gl * c.el;
+    } else {
+        gion = c.g_pas;
+        jion = c.g_pas * c.e_pas;
+    }
+    P = afv * gion;
+    Q = afv * jion;
+}
+
+// Phase B for one compartment: the membrane terms (P, Q, synaptic part
+// included) from the D and R slots, the external current of a root,
+// axial current and diagonal from the couplings to the parent and the
+// children (children in ascending order, as the time-invariant diagonal is
+// defined), then D_i and R_i.
 template <typename T>
 __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const double cdt,
-                                         const T afv, const T m, const T h, const T x,
-                                         double *__restrict__ V, double *__restrict__ R,
+                                         const double *__restrict__ V, double *__restrict__ R,
                                          double *__restrict__ D, const double *__restrict__ Eo,
                                          const Branch *__restrict__ br,
                                          const uint16_t *__restrict__ chl, const T *niext,
-                                         const int neur0, const T gnabar, const T gkbar,
-                                         const T gl, const T ena, const T ek, const T el,
-                                         const T g_pas, const T e_pas, const T e_syn,
-                                         const Consts c) {
+                                         const int neur0, const Consts c) {
     const double v = V[i];
-    const T gs = *(const T *)&R[i];
-    T gion, jion;
-    if (topo_hh(tp)) {
-        const T gna = gnabar * (((m * m) * m) * h);
-        const T gk = gkbar * (((x * x) * x) * x);
-        gion = (gna + gk) + gl;
-        jion = (gna * ena + gk * ek) + gl * el;
-    } else {
-        gion = g_pas;
-        jion = g_pas * e_pas;
-    }
+    const T gmem = *(const T *)&D[i];
+    const T jm = *(const T *)&R[i];
     const bool root = topo_root(tp);
     const T iext = root ? niext[neur0 + topo_parent(tp)] : T(0);
-    const T gmem = afv * gion + gs;
-    const T J = (afv * jion + gs * e_syn) + iext;
+    const T J = jm + iext;
     double ax, d = cdt;
     if (root) {
         ax = 0.0;
@@ -702,6 +735,7 @@ struct Tables {
     int32_t *lvl;
     uint16_t *chl, *scomp, *sseg;
     int32_t *crof;  // contraction round offsets
+    uint64_t *cst;  // contraction items staged in LDS (the schedule's last ones)
 };
 
 template <typename T>
@@ -718,13 +752,26 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
     t.sseg = t.scomp + pk.nsyn;
     char *q = (char *)(t.sseg + pk.nsyn);
     t.crof = (int32_t *)(smem + (((q - smem) + 3) / 4) * 4);
+    char *u = (char *)(t.crof + (pk.nrnd > 0 ? pk.nrnd + 1 : 0));
+    t.cst = (uint64_t *)(smem + (((u - smem) + 7) / 8) * 8);
     return t;
 }
 
+// Compartments per thread whose gates and constants stay in registers for
+// the whole epoch (FP32 gating, contraction solver): compartment tid + j*NT
+// for j < kResident. The rest of a larger pack reads them from global memory
+// each step, as do the level-sweep solvers (whose sweeps already hold most
+// of the register budget) and FP64 gating (whose gates take twice the
+// registers).
+constexpr int kResident = 4;
+
 // One pack through steps [t0, t1) of an epoch. V, R, D and the off-diagonal
 // live at `base` (LDS, or a global scratch slice for packs larger than any
-// LDS budget); gates and per-compartment constants stay in global memory
-// (keeping them in registers costs more occupancy than it saves latency).
+// LDS budget). With FP32 gating each thread holds the gates, area factor,
+// topology word and C/dt of its first kResident compartments in registers,
+// loaded once per epoch; the gates go back to memory at the end.
+// Between the gate update of one step and the assembly of the next, the D
+// and R slots carry each compartment's membrane terms P and Q.
 // In the sweeps the branches of a level go to consecutive lanes (sorted by
 // length on the host), so one wave instruction advances as many chains as
 // the level has branches.
@@ -764,6 +811,8 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         if constexpr (kContract) {
             const int32_t *gro = a.lvl + pk.lv0 + pk.nbw + pk.nfw + 2;
             for (int k = tid; k <= pk.nrnd; k += NT) tb.crof[k] = gro[k];
+            const uint64_t *gst = a.cit + pk.it0 + (pk.ncomp - pk.nst);
+            for (int k = tid; k < pk.nst; k += NT) tb.cst[k] = gst[k];
         }
     }
     double *__restrict__ V = st.V;
@@ -781,19 +830,40 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const uint16_t *chl = tb.chl;
     const int32_t *lvl = tb.lvl;
 
-    const T gnabar = (T)a.gnabar, gkbar = (T)a.gkbar, gl = (T)a.gl;
-    const T ena = (T)a.ena, ek = (T)a.ek, el = (T)a.el;
-    const T g_pas = (T)a.g_pas, e_pas = (T)a.e_pas, e_syn = (T)a.e_syn;
-    const T dt = (T)a.dt, q = (T)a.q;
+    const Chan<T> ch{(T)a.gnabar, (T)a.gkbar, (T)a.gl,    (T)a.ena, (T)a.ek, (T)a.el,
+                     (T)a.g_pas,  (T)a.e_pas, (T)a.e_syn, (T)a.dt,  (T)a.q};
+    const T e_syn = ch.e_syn, dt = ch.dt, q = ch.q;
     const Consts cs{a.omt, a.v_thresh, a.ginv};
     const int t0 = a.t0, t1 = a.t1;
+
+    // resident compartments: tid + j*NT for j < KR; the others from i0 on
+    constexpr int KR = (sizeof(T) == 4 && kContract) ? kResident : 0;
+    constexpr int KA = KR > 0 ? KR : 1;
+    const int i0 = tid + KR * NT;
+    T rm[KA], rh[KA], rx[KA], raf[KA];
+    double rcdt[KA];
+    uint32_t rtp[KA];
 
     // ---- load state -------------------------------------------------------
     for (int i = tid; i < n; i += NT) {
         V[i] = a.V[c0 + i];
         Eo[i] = a.e[c0 + i];
-        R[i] = 0.0;  // synaptic conductance of compartment i in phases A/B
     }
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int i = tid + j * NT;
+        if (i < n) {
+            rm[j] = gm[i];
+            rh[j] = gh[i];
+            rx[j] = gn[i];
+            raf[j] = af[i];
+            rcdt[j] = cdtp[i];
+            rtp[j] = topo[i];
+            membrane<T>(rtp[j], raf[j], rm[j], rh[j], rx[j], ch, *(T *)&D[i], *(T *)&R[i]);
+        }
+    }
+    for (int i = i0; i < n; i += NT)
+        membrane<T>(topo[i], af[i], gm[i], gh[i], gn[i], ch, *(T *)&D[i], *(T *)&R[i]);
     for (int k = tid; k < ns; k += NT) {
         SG[k] = ((const T *)a.sg)[s0 + k];
         st.SM[k] = event_mask(a.ring, a.ring_rows, a.n_neurons, a.E, epoch, a.spre[s0 + k],
@@ -807,7 +877,16 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     MMH_PHASE(0);
 
     for (int t = t0; t < t1; ++t) {
-        // ---- A: delivery and per-compartment synaptic conductance ----------
+        // the resident slots' thread index and topology words pass through
+        // an empty asm once per step: otherwise the compiler hoists their
+        // loop-invariant LDS addresses and loads out of the step loop and
+        // holds them in registers for every slot
+        int tl = tid;
+        asm volatile("" : "+v"(tl));
+#pragma unroll
+        for (int j = 0; j < KR; ++j) asm volatile("" : "+v"(rtp[j]));
+        // ---- A: delivery; each compartment's synaptic conductance joins its
+        // membrane terms (P += g, Q += g E_syn) ------------------------------
         for (int k = tid; k < ns; k += NT) {
             const int L = tb.sseg[k];
             if (L == 0) continue;
@@ -819,16 +898,25 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                 SG[j] = g;
                 sum = sum + g;
             }
-            *(T *)&R[tb.scomp[k]] = sum;
+            const int c = tb.scomp[k];
+            T *P = (T *)&D[c];
+            T *Q = (T *)&R[c];
+            *P = *P + sum;
+            *Q = *Q + sum * e_syn;
         }
         __syncthreads();
         MMH_PHASE(1);
 
-        // ---- B: membrane terms and assembly --------------------------------
+        // ---- B: assembly ------------------------------------------------------
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const int i = tl + j * NT;
+            if (i < n) assemble<T>(i, rtp[j], rcdt[j], V, R, D, Eo, br, chl, niext, pk.neur0, cs);
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll 2
-        for (int i = tid; i < n; i += NT)
-            assemble<T>(i, topo[i], cdtp[i], af[i], gm[i], gh[i], gn[i], V, R, D, Eo, br, chl, niext,
-                        pk.neur0, gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, cs);
+        for (int i = i0; i < n; i += NT)
+            assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, niext, pk.neur0, cs);
         __syncthreads();
         MMH_PHASE(2);
 
@@ -841,18 +929,26 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             // every thread takes items of each round, a workgroup barrier
             // between rounds; the items stay in global memory (L2), and each
             // thread reads its first item of the next round before working on
-            // the current one, so the read overlaps the round and its barrier
+            // the current one, so the read overlaps the round and its barrier.
+            // The tail of small rounds (at most one wavefront's worth of
+            // items each) runs on the first wavefront alone, which needs no
+            // workgroup barrier between rounds: its lanes run in lockstep, so
+            // waiting for its own LDS writes to complete is enough.
             const uint64_t *__restrict__ cit = a.cit + pk.it0;
             const int32_t *rof = tb.crof;
-            const int nr = pk.nrnd;
+            const int nr = pk.nrnd, nw = pk.nrw, qs = n - pk.nst;
+            const uint64_t *cst = tb.cst;  // item q >= qs staged at cst[q - qs]
+            auto item = [&](int q, int end) -> uint64_t {
+                return q < end ? (q >= qs ? cst[q - qs] : cit[q]) : 0ull;
+            };
             {
                 int lo = rof[0], hi = rof[nr > 0 ? 1 : 0];
-                uint64_t cur = (lo + tid < hi) ? cit[lo + tid] : 0ull;
-                for (int r = 0; r < nr; ++r) {
+                uint64_t cur = item(lo + tid, hi);
+                for (int r = 0; r < nw; ++r) {
                     // the next round's end and first item, read before this
                     // round's work and barrier
                     const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
-                    const uint64_t nxt = (hi + tid < hi2) ? cit[hi + tid] : 0ull;
+                    const uint64_t nxt = item(hi + tid, hi2);
                     if (lo + tid < hi) contract_elim(D, R, V, cur);
                     for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
                         contract_elim(D, R, V, cit[q2]);
@@ -861,14 +957,39 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     hi = hi2;
                     cur = nxt;
                 }
+                if (tid < kWave) {
+                    for (int r = nw; r < nr; ++r) {
+                        const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
+                        const uint64_t nxt = item(hi + tid, hi2);
+                        if (lo + tid < hi) contract_elim(D, R, V, cur);
+                        wave_lds_sync();
+                        lo = hi;
+                        hi = hi2;
+                        cur = nxt;
+                    }
+                    MMH_PHASE(3);
+                    // back substitution of the tail, in reverse round order
+                    hi = rof[nr];
+                    lo = rof[nr > 0 ? nr - 1 : 0];
+                    cur = item(lo + tid, hi);
+                    for (int r = nr - 1; r >= nw; --r) {
+                        const int lo2 = (r > 0) ? rof[r - 1] : lo;
+                        const uint64_t nxt = item(lo2 + tid, lo);
+                        if (lo + tid < hi) contract_subst(R, D, V, cur);
+                        wave_lds_sync();
+                        hi = lo;
+                        lo = lo2;
+                        cur = nxt;
+                    }
+                }
+                __syncthreads();
             }
-            MMH_PHASE(3);
             {
-                int hi = rof[nr], lo = rof[nr > 0 ? nr - 1 : 0];
-                uint64_t cur = (lo + tid < hi) ? cit[lo + tid] : 0ull;
-                for (int r = nr - 1; r >= 0; --r) {
+                int hi = rof[nw], lo = rof[nw > 0 ? nw - 1 : 0];
+                uint64_t cur = item(lo + tid, hi);
+                for (int r = nw - 1; r >= 0; --r) {
                     const int lo2 = (r > 0) ? rof[r - 1] : lo;
-                    const uint64_t nxt = (lo2 + tid < lo) ? cit[lo2 + tid] : 0ull;
+                    const uint64_t nxt = item(lo2 + tid, lo);
                     if (lo + tid < hi) contract_subst(R, D, V, cur);
                     for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
                         contract_subst(R, D, V, cit[q2]);
@@ -932,17 +1053,32 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         MMH_PHASE(4);
         }  // level-synchronous solvers
 
-        // ---- E: gates at V^{n+1}; detection --------------------------------
+        // ---- E: gates at V^{n+1}, the next step's membrane terms; detection
+        const bool more = t + 1 < t1;
+#pragma unroll
+        for (int j = 0; j < KR; ++j) {
+            const int i = tl + j * NT;
+            if (i < n) {
+                if (topo_hh(rtp[j])) gates_update<T>(V[i], rm[j], rh[j], rx[j], dt);
+                if (more)
+                    membrane<T>(rtp[j], raf[j], rm[j], rh[j], rx[j], ch, *(T *)&D[i],
+                                *(T *)&R[i]);
+            }
+            // one compartment's gate update at a time: interleaving them
+            // would hold several sets of rate temporaries live at once
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll 1
-        for (int i = tid; i < n; i += NT) {
-            if (topo_hh(topo[i])) {
-                T m = gm[i], h = gh[i], x = gn[i];
+        for (int i = i0; i < n; i += NT) {
+            const uint32_t tp = topo[i];
+            T m = gm[i], h = gh[i], x = gn[i];
+            if (topo_hh(tp)) {
                 gates_update<T>(V[i], m, h, x, dt);
                 gm[i] = m;
                 gh[i] = h;
                 gn[i] = x;
             }
-            R[i] = 0.0;
+            if (more) membrane<T>(tp, af[i], m, h, x, ch, *(T *)&D[i], *(T *)&R[i]);
         }
         for (int k = tid; k < nn; k += NT) {
             const double vn = V[a.ndet[pk.neur0 + k]];
@@ -955,6 +1091,15 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 
     // ---- write back -----------------------------------------------------------
     for (int i = tid; i < n; i += NT) a.V[c0 + i] = V[i];
+#pragma unroll
+    for (int j = 0; j < KR; ++j) {
+        const int i = tid + j * NT;
+        if (i < n && topo_hh(rtp[j])) {
+            gm[i] = rm[j];
+            gh[i] = rh[j];
+            gn[i] = rx[j];
+        }
+    }
     if (t1 > t0) {
         T *osg = (T *)a.sg;
         for (int k = tid; k < ns; k += NT) osg[s0 + k] = q * SG[k];

@@ -46,7 +46,7 @@ def imbalance(n_neurons: int = 10000, steps: int = 400, warmup: int = 40, seed: 
     """Mono vs multi-morphology under plain, count and learned packing."""
     mono = W.size_group(seed, n_neurons, mono=True)
     multi = W.size_group(seed, n_neurons, mono=False)
-    model = costmodel.load_or_train()
+    model = costmodel.load_or_train(solver=solver)
     runs = {
         "mono_plain": _time(mono, S.PACK_PLAIN, steps, warmup, solver),
         "mono_count": _time(mono, S.PACK_COUNT, steps, warmup, solver),
@@ -72,10 +72,10 @@ def main():
     ap.add_argument("--neurons", type=int, default=10000)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--solver", default="fast", choices=["exact", "fast"])
+    ap.add_argument("--solver", default="fast", choices=["exact", "fast", "contract"])
     args = ap.parse_args()
-    out = imbalance(args.neurons, args.steps, args.warmup,
-                    solver=S.SOLVE_FAST if args.solver == "fast" else S.SOLVE_EXACT)
+    solver = dict(exact=S.SOLVE_EXACT, fast=S.SOLVE_FAST, contract=S.SOLVE_CONTRACT)[args.solver]
+    out = imbalance(args.neurons, args.steps, args.warmup, solver=solver)
     print(json.dumps(out), flush=True)
 
 

@@ -82,6 +82,7 @@ class PackInfo(C.Structure):
         ("in_global", C.c_int32), ("n_rounds", C.c_int32), ("n_levels", C.c_int32),
         ("n_child_entries", C.c_int32), ("table_bytes", C.c_int64),
         ("state_bytes", C.c_int64), ("cost", C.c_double),
+        ("n_wide_rounds", C.c_int32), ("n_staged_items", C.c_int32),
     ]
 
 

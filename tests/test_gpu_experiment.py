@@ -32,7 +32,7 @@ def say(*a):
 @pytest.fixture(scope="module")
 def cost_model(S):
     from paper_2005_06332_amd import costmodel
-    return costmodel.load_or_train()
+    return costmodel.load_or_train(solver=S.SOLVE_CONTRACT)
 
 
 @pytest.mark.parametrize("mono", [False, True])

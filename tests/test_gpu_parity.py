@@ -7,10 +7,10 @@ Voltage tolerances:
   both precision modes; in practice the results are bitwise equal, and the
   tests report how many voltages differ at all.
 - fast solver (division-free homogeneous elimination) and contraction
-  solver (tree contraction), FP64: 1e-9 mV. Its
-  per-step rounding differs from the oracle's by a few ulps of V (about
-  1e-14 mV), measured at 2.6e-11 mV after 200 steps of the full network.
-- fast solver, FP32 gating: 1e-4 mV. The gates see (float)V; a V that
+  solver (tree contraction), FP64: 1e-9 mV. Their per-step rounding
+  differs from the oracle's by a few ulps of V (about 1e-14 mV); the fast
+  solver measured 2.6e-11 mV after 200 steps of the full network.
+- fast and contraction solvers, FP32 gating: 1e-4 mV. The gates see (float)V; a V that
   differs by 1e-14 mV rounds to the other neighbouring float in about one
   case in 1e8 compartment-steps, and each such case moves a gate by one
   float ulp (6e-8 relative), which moves V by up to about 1e-5 mV over the
@@ -209,12 +209,12 @@ def test_validation_errors_do_not_touch_the_device(S):
 
 def test_full_size_multimorphology_matches_oracle(S, orc):
     """The 16384-neuron multi-morphology network (9.29e6 compartments, 1.6e6
-    synapses) in the launch configuration bench.py times (count packing,
-    autotuned layout, fast solver, FP32 gating), 200 steps = 5 epochs, every
-    voltage and every spike against the FP32-gating oracle (stated bound
-    1e-4 mV) and against the FP64 oracle (the error of FP32 gating itself,
-    stated bound 1e-2 mV; measured 2.8e-4 mV), then the exact solver against
-    the FP32-gating oracle at 1e-9 mV."""
+    synapses) with count packing and FP32 gating, 200 steps = 5 epochs, every
+    voltage and every spike: the fast and the contraction solver (the latter
+    in the launch configuration bench.py times, autotuned layout) against
+    the FP32-gating oracle (stated bound 1e-4 mV) and against the FP64 oracle
+    (the error of FP32 gating itself, stated bound 1e-2 mV), then the exact
+    solver against the FP32-gating oracle at 1e-9 mV."""
     prob = W.make(3)
     steps = 200
     say(f"case full cfg3 N={prob['n_comp'].shape[0]} C={int(prob['comp_off'][-1])} steps={steps}")
@@ -266,14 +266,14 @@ def test_other_full_size_configs_match_oracle(S, orc, cfg, precision, solver, st
 @pytest.mark.parametrize("solver", [0, 1, 2])
 def test_full_length_replay_matches_oracle(S, orc, solver):
     """Per-neuron replay over the whole 4000-step run of the 16384-neuron
-    network: the GPU runs the full network (bench.py's configuration for
-    the fast solver); 34 neurons (32 drawn with a fixed seed, the largest
+    network: the GPU runs the full network (for the contraction solver,
+    bench.py's configuration); 34 neurons (32 drawn with a fixed seed, the largest
     and the smallest) are then rerun in the oracle, fed with the GPU's
     recorded spikes of their presynaptic neurons. This separates numerics
     from network chaos over the full length: every voltage of those neurons
     after 4000 steps and every one of their spikes must match (exact solver
-    1e-9 mV, measured bitwise; fast solver with FP32 gating 1e-4 mV,
-    measured 1.2e-5 mV)."""
+    1e-9 mV, measured bitwise; fast and contraction solvers with FP32 gating
+    1e-4 mV)."""
     prob = W.make(3)
     N = prob["n_comp"].shape[0]
     steps = 4000
@@ -352,3 +352,25 @@ def test_one_long_call_equals_chunked_calls_and_oracle(S, orc, solver):
     vr, sr = ref.voltages(), ref.spikes()
     ref.close()
     compare(f"mini one call of {steps} steps solver={solver}", v1, vr, s1, sr, tol(1, solver))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_contraction_wide_rounds_tail_and_staging_match_oracle(S, orc, precision):
+    """Packs of about 900 compartments, as bench.py lays them out: their
+    first contraction rounds run across the whole workgroup, the tail of
+    small rounds on one wavefront, with some or all of the tail's items
+    staged in LDS and the rest read from global memory. Every voltage, gate,
+    conductance and spike after 120 steps against the oracle."""
+    prob = W.subset(W.make(3), np.arange(1200))
+    with S.Simulation(prob, solver=2, precision=precision, plan=(160 * 1024, 256),
+                      lds_classes=3) as g:
+        infos = [g.pack_info(p) for p in range(g.pack_count())]
+    assert any(i["n_wide_rounds"] > 0 for i in infos)
+    assert any(0 < i["n_wide_rounds"] < i["n_rounds"] for i in infos)
+    assert any(i["n_staged_items"] > 0 for i in infos)
+    (v, s, gt, gs), (vr, sr, gtr, gsr) = run_pair(S, orc, prob, 120, precision, solver=2,
+                                                  lds_classes=3)
+    compare(f"wide+tail contraction prec={precision}", v, vr, s, sr, tol(precision, 2))
+    for a, b in zip(gt, gtr):
+        assert np.max(np.abs(np.asarray(a, np.float64) - b)) <= (1e-5 if precision else 1e-9)
+    assert np.max(np.abs(np.asarray(gs, np.float64) - gsr)) <= 1e-9

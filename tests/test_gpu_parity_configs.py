@@ -2,12 +2,12 @@
 of FP32 gating against the FP64 oracle per workload.
 
 - cfg2 (8192 identical neurons of 1000 compartments) with FP32 gating and
-  FP64 Hines, both solvers, every voltage and spike after 80 steps.
+  FP64 Hines, all three solvers, every voltage and spike after 80 steps.
 - cfg4 (32768 multi-morphology neurons) with learned packing (the MLP cost
-  model trained on kernel timings), both solvers, every voltage and spike
-  after 80 steps.
+  model trained on kernel timings), all three solvers, every voltage and
+  spike after 80 steps.
 - Full-length per-neuron replay: the GPU runs a whole network for 4000 steps
-  in the configuration bench.py times (fast solver, FP32 gating); 34 of its
+  in the configuration bench.py times (contraction solver, FP32 gating); 34 of its
   neurons (32 drawn with a fixed seed, the largest and the smallest) are
   rerun in the oracle fed with the GPU's recorded presynaptic spikes:
     * in the FP32-gating oracle: voltages within 1e-4 mV, identical spikes;
@@ -40,7 +40,7 @@ FP32_VS_FP64_BOUND_MV = 0.5
 
 
 def tol(precision, solver):
-    return TOL_FAST_FP32_MV if (solver == 1 and precision == 1) else TOL_MV
+    return TOL_FAST_FP32_MV if (solver != 0 and precision == 1) else TOL_MV
 
 
 @pytest.fixture(scope="module")
@@ -78,10 +78,10 @@ def full_pair(S, orc, prob, steps, precision, **kw):
     return v, s, vr, sr
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_cfg2_fp32_gating_full_size(S, orc, solver):
     prob = W.make(2)
-    v, s, vr, sr = full_pair(S, orc, prob, 80, 1, solver=solver, autotune=(solver == 1))
+    v, s, vr, sr = full_pair(S, orc, prob, 80, 1, solver=solver, autotune=(solver != 0))
     compare(f"full cfg2 FP32 gating solver={solver}", v, vr, s, sr, tol(1, solver))
 
 
@@ -91,7 +91,7 @@ def cost_model(S):
     return costmodel.load_or_train()
 
 
-@pytest.mark.parametrize("solver", [0, 1])
+@pytest.mark.parametrize("solver", [0, 1, 2])
 def test_cfg4_learned_packing_full_size(S, orc, cost_model, solver):
     prob = W.make(4)
     v, s, vr, sr = full_pair(S, orc, prob, 80, 1, solver=solver, packing=S.PACK_LEARNED,
@@ -150,7 +150,7 @@ def fp32_error_report(S, orc, name, prob, steps=4000, **kw):
     targets = replay_targets(prob)
     N = prob["n_comp"].shape[0]
     say(f"case {name} full-length replay steps={steps} targets={len(targets)}")
-    with S.Simulation(prob, precision=1, solver=1, **kw) as g:
+    with S.Simulation(prob, precision=1, solver=2, **kw) as g:
         say("  config:", g.config)
         g.step(steps)
         v, s = g.voltages(), g.spikes()
@@ -160,7 +160,7 @@ def fp32_error_report(S, orc, name, prob, steps=4000, **kw):
     gsp = gpu_spikes_of(s, targets)
     # FP32-gating oracle: parity
     v32, sp32, _ = replay(orc, prob, targets, raster, steps, 1)
-    compare(f"{name} replay fast vs FP32-gating oracle", want, v32, gsp, sp32,
+    compare(f"{name} replay contract vs FP32-gating oracle", want, v32, gsp, sp32,
             TOL_FAST_FP32_MV)
     # FP64 oracle: the error of FP32 gating
     v64, sp64, vdet = replay(orc, prob, targets, raster, steps, 0, track=True)

@@ -41,13 +41,16 @@ def table_bytes(info, tsize):
     """Tables as the kernel carves them: branch records (16 B), synapse
     weights, level offsets (4 B, 4-aligned), forward order and child list
     (2 B each), synapse targets and run lengths (2 B each); then, for the
-    contraction solver, round offsets (4 B; its items stay in global
-    memory); the whole rounded to 16 B."""
+    contraction solver, round offsets (4 B) and the items staged in LDS
+    (8 B, 8-aligned; the others stay in global memory); the whole rounded to
+    16 B."""
     b = 16 * info["n_branches"] + tsize * info["n_syn"]
     b = align(b, 4) + 4 * info["n_levels"]
     b += 2 * info["n_branches"] + 2 * info["n_child_entries"] + 4 * info["n_syn"]
     if info["n_rounds"] > 0:
         b = align(b, 4) + 4 * (info["n_rounds"] + 1)
+    if info["n_staged_items"] > 0:
+        b = align(b, 8) + 8 * info["n_staged_items"]
     return align(b, 16)
 
 
@@ -265,3 +268,28 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
             x = execute_schedule(items, ro, p, e, d, rhs)
             ref = np.linalg.solve(A, rhs)
             assert np.max(np.abs(x - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("which", ["cfg3 subset", "cfg1", "star"])
+def test_contraction_tail_rounds_fit_one_wavefront(S, which):
+    """A pack's round r is round r of each of its neurons; rounds from
+    n_wide_rounds on hold at most 64 items (one wavefront runs them without
+    workgroup barriers), and the round before them holds more."""
+    prob = {"cfg3 subset": lambda: W.subset(W.make(3), np.arange(400)),
+            "cfg1": W.config1, "star": W.star_network}[which]()
+    off = prob["comp_off"]
+    with plan(S, prob, solver=2) as g:
+        for p in range(g.pack_count()):
+            info = g.pack_info(p)
+            sizes = np.zeros(info["n_rounds"], np.int64)
+            for j in g.pack_neurons(p):
+                _, ro = g.contraction_schedule(int(j), int(off[j + 1] - off[j]))
+                sizes[:len(ro) - 1] += np.diff(ro)
+            assert sizes.sum() == info["n_comp"]
+            nw = info["n_wide_rounds"]
+            assert 0 <= nw <= info["n_rounds"]
+            assert np.all(sizes[nw:] <= 64), (p, nw, sizes)
+            if nw > 0:
+                assert sizes[nw - 1] > 64, (p, nw, sizes)
+            # the staged items are a suffix of the tail
+            assert 0 <= info["n_staged_items"] <= sizes[nw:].sum()
