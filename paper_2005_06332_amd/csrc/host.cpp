@@ -1573,7 +1573,8 @@ int lds_for(const sim_t *s, int comps) {
 void autotune(sim_t *s, Variant base) {
     // (pack_comps, LDS budget in compartments): small packs keep more
     // workgroups resident per CU, which hides the latency of the sweeps
-    static const int kShapes[][2] = {{600, 800}, {800, 1100}, {1000, 1300}, {1400, 1800}};
+    static const int kShapes[][2] = {{300, 420},  {400, 550},   {500, 680},  {600, 800},
+                                     {800, 1100}, {1000, 1300}, {1400, 1800}};
     std::vector<Variant> cand;
     for (int thr : {128, 256, 320})
         for (const auto &sh : kShapes) {

@@ -141,6 +141,7 @@ template <typename T>
 __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_t k) {
     int64_t b = 4 * 8 * n;                 // V, R, D, off-diagonal
     b += 8 * s + 8 * k + 8 * k;            // synapse masks, spike masks, V_det
+    b += 8 * k + 8 * k;                    // external current, detector index
     b += ((int64_t)sizeof(T) * s + 15) / 16 * 16;  // synaptic conductances
     b += 64;  // slack: the blocked sweeps read up to 3 doubles past a branch
     return b;

@@ -278,6 +278,8 @@ template <typename T>
 struct State {
     double *V, *R, *D, *Eo, *VO;
     uint64_t *SM, *SP;
+    double *IX;    // per neuron: external current (a T in an 8-byte slot)
+    int32_t *ND;   // per neuron: detector compartment (pack-local; 8-byte slots)
     T *SG;
 };
 
@@ -293,7 +295,9 @@ __device__ __forceinline__ State<T> carve(char *base, int n, int s, int k) {
     p.SM = up;
     p.SP = up + s;
     p.VO = (double *)(up + s + k);
-    p.SG = (T *)(p.VO + k);
+    p.IX = p.VO + k;
+    p.ND = (int32_t *)(p.IX + k);
+    p.SG = (T *)(p.ND + 2 * k);
     return p;
 }
 
@@ -679,13 +683,13 @@ __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const d
                                          const double *__restrict__ V, double *__restrict__ R,
                                          double *__restrict__ D, const double *__restrict__ Eo,
                                          const Branch *__restrict__ br,
-                                         const uint16_t *__restrict__ chl, const T *niext,
-                                         const int neur0, const Consts c) {
+                                         const uint16_t *__restrict__ chl,
+                                         const double *__restrict__ IX, const Consts c) {
     const double v = V[i];
     const T gmem = *(const T *)&D[i];
     const T jm = *(const T *)&R[i];
     const bool root = topo_root(tp);
-    const T iext = root ? niext[neur0 + topo_parent(tp)] : T(0);
+    const T iext = root ? *(const T *)&IX[topo_parent(tp)] : T(0);
     const T J = jm + iext;
     double ax, d = cdt;
     if (root) {
@@ -826,6 +830,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const double *cdtp = a.cdt + c0;
     const uint32_t *topo = a.topo + c0;
     const T *niext = (const T *)a.niext;
+    double *__restrict__ IX = st.IX;
     const Branch *br = tb.br;
     const uint16_t *chl = tb.chl;
     const int32_t *lvl = tb.lvl;
@@ -870,7 +875,10 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                               a.sdelay[s0 + k]);
     }
     for (int k = tid; k < nn; k += NT) {
-        st.VO[k] = a.V[c0 + a.ndet[pk.neur0 + k]];
+        const int32_t det = a.ndet[pk.neur0 + k];
+        st.VO[k] = a.V[c0 + det];
+        st.ND[2 * k] = det;
+        *(T *)&IX[k] = niext[pk.neur0 + k];
         st.SP[k] = 0ull;
     }
     __syncthreads();
@@ -911,12 +919,12 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 #pragma unroll
         for (int j = 0; j < KR; ++j) {
             const int i = tl + j * NT;
-            if (i < n) assemble<T>(i, rtp[j], rcdt[j], V, R, D, Eo, br, chl, niext, pk.neur0, cs);
+            if (i < n) assemble<T>(i, rtp[j], rcdt[j], V, R, D, Eo, br, chl, IX, cs);
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll 2
         for (int i = i0; i < n; i += NT)
-            assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, niext, pk.neur0, cs);
+            assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, IX, cs);
         __syncthreads();
         MMH_PHASE(2);
 
@@ -1081,7 +1089,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             if (more) membrane<T>(tp, af[i], m, h, x, ch, *(T *)&D[i], *(T *)&R[i]);
         }
         for (int k = tid; k < nn; k += NT) {
-            const double vn = V[a.ndet[pk.neur0 + k]];
+            const double vn = V[st.ND[2 * k]];
             if (st.VO[k] < cs.vth && vn >= cs.vth) st.SP[k] |= 1ull << t;
             st.VO[k] = vn;
         }

@@ -56,10 +56,11 @@ def table_bytes(info, tsize):
 
 def state_bytes(info, tsize):
     """V, R, D and the off-diagonal (8 B per compartment each), synapse event
-    masks (8 B), spike masks and detector voltages (8 B per neuron each),
-    synaptic conductances (16-aligned), 64 B of sweep slack."""
+    masks (8 B), spike masks, detector voltages, external currents and
+    detector indices (8 B per neuron each), synaptic conductances
+    (16-aligned), 64 B of sweep slack."""
     n, s, k = info["n_comp"], info["n_syn"], info["n_neurons"]
-    return 32 * n + 8 * s + 16 * k + align(tsize * s, 16) + 64
+    return 32 * n + 8 * s + 32 * k + align(tsize * s, 16) + 64
 
 
 CASES = [
