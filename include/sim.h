@@ -212,8 +212,9 @@ typedef struct {
     int64_t state_bytes;    /* bytes of its state (LDS unless in_global) */
     double cost;            /* packing cost (compartments, or predicted time) */
     int32_t n_wide_rounds;  /* contraction: leading rounds run by the whole
-                               workgroup; the later ones, at most 64 items
-                               each, by its first wavefront alone */
+                               workgroup; the later ones (at most 64 items
+                               each, every item staged in LDS) by its first
+                               wavefront alone */
     int32_t n_staged_items; /* contraction: the last items of the pack's
                                schedule (the single-wavefront tail) copied
                                to LDS, as many as the class's LDS budget

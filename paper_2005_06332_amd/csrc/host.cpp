@@ -1046,6 +1046,13 @@ void build_layout(sim_t *s, Variant v) {
                 --nst;
             d.nst = (int32_t)nst;
             d.tbytes = (int32_t)tb_with(nst);
+            // the single-wavefront tail reads its items from LDS only: it
+            // starts at the first round whose items are all staged; and its
+            // lanes hold its round offsets, one per lane, so it spans at
+            // most kWave - 1 rounds (a soma of high fan-out loses one child
+            // per round and can need many more)
+            while (d.nrw < d.nrnd && ro[d.nrw] < d.ncomp - d.nst) ++d.nrw;
+            d.nrw = std::max(d.nrw, d.nrnd - (kWave - 1));
         }
         if (!d.global_mem) {
             lds_cls[c] = std::max(lds_cls[c], d.tbytes + bytes);

@@ -58,7 +58,8 @@ struct PackDesc {
     int32_t tbytes;        // bytes of staged tables (always in LDS)
     int32_t it0, nrnd;     // contraction solver: first item, rounds (0: other solvers)
     int32_t nrw;           // contraction rounds [0, nrw) run by the whole workgroup,
-                           // rounds [nrw, nrnd) (at most kWave items each) by its
+                           // rounds [nrw, nrnd) (at most kWave - 1 of them, at
+                           // most kWave items each, all staged in LDS) by its
                            // first wavefront alone, with no workgroup barrier
     int32_t nst;           // contraction: the last nst items staged in LDS
 };

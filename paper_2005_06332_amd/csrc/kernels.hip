@@ -631,13 +631,14 @@ __device__ __forceinline__ void contract_subst(const double *__restrict__ R,
     V[k] = x;
 }
 
-// Makes this wavefront's LDS writes visible to all of its lanes: waits for
-// them to complete and keeps the compiler from moving LDS accesses across
-// (a workgroup-scope release/acquire pair without the workgroup barrier).
+// Orders this wavefront's LDS accesses across lanes: LDS performs a
+// wavefront's instructions in issue order, so a read issued after a write
+// (by any lane of the same wavefront) sees it; only the compiler must be kept
+// from moving accesses across (a wavefront-scope fence, which waits for
+// nothing).
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 struct Consts {
@@ -966,9 +967,21 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     cur = nxt;
                 }
                 if (tid < kWave) {
+                    // the tail's items are all staged in LDS (the host moves
+                    // the tail's start past any round that is not), and lane
+                    // l holds the round offset rof[nw + l]: the next round's
+                    // bounds come from a register, not a dependent LDS read
+                    const int rl = (nw + tid <= nr) ? rof[nw + tid] : 0;
+                    auto rofw = [&](int r) { return __builtin_amdgcn_readlane(rl, r - nw); };
+                    // (reads clamped into the staged range rather than
+                    // branched around, so that no wait is needed before the
+                    // current round's own reads)
+                    const int qmax = pk.nst - 1;
+                    auto tail_item = [&](int q) { return cst[max(0, min(q - qs, qmax))]; };
+                    if (nw < nr) cur = tail_item(lo + tid);
                     for (int r = nw; r < nr; ++r) {
-                        const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
-                        const uint64_t nxt = item(hi + tid, hi2);
+                        const int hi2 = (r + 1 < nr) ? rofw(r + 2) : hi;
+                        const uint64_t nxt = tail_item(hi + tid);
                         if (lo + tid < hi) contract_elim(D, R, V, cur);
                         wave_lds_sync();
                         lo = hi;
@@ -977,12 +990,14 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     }
                     MMH_PHASE(3);
                     // back substitution of the tail, in reverse round order
-                    hi = rof[nr];
-                    lo = rof[nr > 0 ? nr - 1 : 0];
-                    cur = item(lo + tid, hi);
+                    if (nw < nr) {
+                        hi = rofw(nr);
+                        lo = rofw(nr - 1);
+                        cur = tail_item(lo + tid);
+                    }
                     for (int r = nr - 1; r >= nw; --r) {
-                        const int lo2 = (r > 0) ? rof[r - 1] : lo;
-                        const uint64_t nxt = item(lo2 + tid, lo);
+                        const int lo2 = (r - 1 >= nw) ? rofw(r - 1) : lo;
+                        const uint64_t nxt = tail_item(lo2 + tid);
                         if (lo + tid < hi) contract_subst(R, D, V, cur);
                         wave_lds_sync();
                         hi = lo;

@@ -274,8 +274,11 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
 @pytest.mark.parametrize("which", ["cfg3 subset", "cfg1", "star"])
 def test_contraction_tail_rounds_fit_one_wavefront(S, which):
     """A pack's round r is round r of each of its neurons; rounds from
-    n_wide_rounds on hold at most 64 items (one wavefront runs them without
-    workgroup barriers), and the round before them holds more."""
+    n_wide_rounds on (at most 63 of them) hold at most 64 items and are
+    staged in LDS whole (one wavefront runs them without workgroup
+    barriers), and the round before them holds more, is not staged whole,
+    or would make the tail longer than 63 rounds (a soma with 64 children
+    needs more than 64 rounds)."""
     prob = {"cfg3 subset": lambda: W.subset(W.make(3), np.arange(400)),
             "cfg1": W.config1, "star": W.star_network}[which]()
     off = prob["comp_off"]
@@ -289,8 +292,18 @@ def test_contraction_tail_rounds_fit_one_wavefront(S, which):
             assert sizes.sum() == info["n_comp"]
             nw = info["n_wide_rounds"]
             assert 0 <= nw <= info["n_rounds"]
+            st = info["n_staged_items"]
+            nr = info["n_rounds"]
             assert np.all(sizes[nw:] <= 64), (p, nw, sizes)
+            assert st >= sizes[nw:].sum()
+            # the tail's lanes hold its round offsets: at most 63 rounds
+            assert nr - nw <= 63
             if nw > 0:
-                assert sizes[nw - 1] > 64, (p, nw, sizes)
-            # the staged items are a suffix of the tail
-            assert 0 <= info["n_staged_items"] <= sizes[nw:].sum()
+                assert (sizes[nw - 1] > 64 or st < sizes[nw - 1:].sum()
+                        or nr - nw == 63), (p, nw, sizes, st)
+            # the staged items are a suffix of the tail rounds (those that
+            # hold at most 64 items each)
+            small = len(sizes)
+            while small > 0 and sizes[small - 1] <= 64:
+                small -= 1
+            assert 0 <= st <= sizes[small:].sum()
