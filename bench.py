@@ -265,17 +265,19 @@ def main():
 
     # HBM bytes per launch measured with rocprofv3 counters on this kernel
     # source (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known
-    # size); reported only while the kernel source is unchanged and for a
-    # launch of the profiled length.
+    # size), one record per profiled layout; reported only while the kernel
+    # source is unchanged, for the same layout and a launch of the profiled
+    # length.
     traffic = None
     tfile = os.path.join(ROOT, "profiles", f"traffic_{prob['name']}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             rec = json.load(f)
-        if (rec.get("kernel_source_sha1") == kernel_source_hash()
-                and abs(rec.get("steps_per_launch", -1) - steps_per_launch) < 1e-9
-                and rec.get("launch") == config_str):
-            traffic = rec.get("bytes_per_launch")
+        if rec.get("kernel_source_sha1") == kernel_source_hash():
+            for lay in rec.get("layouts", []):
+                if (abs(lay.get("steps_per_launch", -1) - steps_per_launch) < 1e-9
+                        and lay.get("launch") == config_str):
+                    traffic = lay.get("bytes_per_launch")
 
     out = {
         "metric": METRIC,
