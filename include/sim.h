@@ -156,6 +156,11 @@ typedef struct {
                                   SIM_PACK_LEARNED, or NULL */
     void *hip_stream;    /* hipStream_t to launch on; NULL = the library's
                             own stream */
+    const double *neuron_cost; /* SIM_PACK_LEARNED: per-neuron costs
+                                  (n_neurons finite values > 0, input order)
+                                  used in place of the cost model's
+                                  predictions, e.g. measured times; NULL =
+                                  the model */
 } sim_params_t;
 
 typedef struct {

@@ -319,6 +319,7 @@ struct sim {
     std::vector<double> length, diam, iext, weight;
     std::vector<uint8_t> mech;
     std::vector<float> cost_model;
+    std::vector<double> ncost;  // per-neuron costs given for learned packing
     int precision = 1;
     int solver = 0;
     int E = 40;
@@ -514,6 +515,11 @@ void validate(const sim_params_t *P, const sim_morphology_t *M, const sim_channe
         for (int64_t i = 0; i < kMlpParams; ++i)
             if (!std::isfinite(P->cost_model[i])) throw fail(SIM_EINVAL, "non-finite cost model");
     }
+    if (P->packing == SIM_PACK_LEARNED && P->neuron_cost) {
+        for (int32_t j = 0; j < M->n_neurons; ++j)
+            if (!std::isfinite(P->neuron_cost[j]) || !(P->neuron_cost[j] > 0.0))
+                throw fail(SIM_EINVAL, "neuron %d: cost must be finite and > 0", j);
+    }
 }
 
 void copy_inputs(sim_t *s, const sim_params_t *P, const sim_morphology_t *M,
@@ -538,6 +544,9 @@ void copy_inputs(sim_t *s, const sim_params_t *P, const sim_morphology_t *M,
         s->weight.assign(SY->weight_uS, SY->weight_uS + s->S);
     }
     if (P->cost_model) s->cost_model.assign(P->cost_model, P->cost_model + kMlpParams);
+    if (P->packing == SIM_PACK_LEARNED && P->neuron_cost)
+        s->ncost.assign(P->neuron_cost, P->neuron_cost + s->N);
+    s->P.neuron_cost = nullptr;  // copied; the caller's array need not outlive the call
     s->precision = P->precision;
     s->solver = P->solver;
     s->tsize = P->precision == SIM_FP64 ? 8 : 4;
@@ -610,10 +619,15 @@ int32_t contraction_rounds(const sim_t *s, int32_t j) {
     return s->croff0.size() > (size_t)j + 1 ? (int32_t)(s->croff0[j + 1] - s->croff0[j] - 1) : 0;
 }
 
+bool learned_costs(const sim_t *s) {
+    return s->P.packing == SIM_PACK_LEARNED && (!s->cost_model.empty() || !s->ncost.empty());
+}
+
 void compute_cost(sim_t *s) {
     s->cost.assign(s->N, 0.0);
-    const bool learned = s->P.packing == SIM_PACK_LEARNED && !s->cost_model.empty();
-    if (learned) {
+    if (s->P.packing == SIM_PACK_LEARNED && !s->ncost.empty()) {
+        s->cost = s->ncost;
+    } else if (learned_costs(s)) {
         std::vector<float> pred(s->N);
         hipError_t e = mlp_forward(s->cost_model.data(), s->feat.data(), s->N, pred.data());
         if (e != hipSuccess) throw fail(SIM_EDEVICE, "cost model inference failed: %s", hipGetErrorString(e));
@@ -639,7 +653,7 @@ void build_layout(sim_t *s, Variant v) {
     std::iota(s->order.begin(), s->order.end(), 0);
     // count and learned packing fill their packs in decreasing compartment
     // count (ties by cost); the cost then orders the packs
-    const bool learned = s->P.packing == SIM_PACK_LEARNED && !s->cost_model.empty();
+    const bool learned = learned_costs(s);
     if (s->P.packing != SIM_PACK_PLAIN)
         std::stable_sort(s->order.begin(), s->order.end(), [&](int32_t a, int32_t b) {
             const int64_t na = s->off[a + 1] - s->off[a], nb = s->off[b + 1] - s->off[b];
@@ -1554,6 +1568,7 @@ std::string describe(const sim_t *s) {
              : s->solver == SIM_SOLVE_CONTRACT ? "contract" : "exact",
              s->P.packing == SIM_PACK_PLAIN ? "plain"
              : s->P.packing == SIM_PACK_COUNT ? "count"
+             : !s->ncost.empty() ? "learned(given costs)"
              : s->cost_model.empty() ? "learned(fallback count)" : "learned");
     return buf;
 }

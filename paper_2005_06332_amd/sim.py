@@ -51,6 +51,7 @@ class Params(C.Structure):
         ("pack_comps", C.c_int32), ("lds_comps", C.c_int32), ("lds_classes", C.c_int32),
         ("use_graph", C.c_int32),
         ("record_timings", C.c_int32), ("cost_model", C.c_void_p), ("hip_stream", C.c_void_p),
+        ("neuron_cost", C.c_void_p),
     ]
 
 
@@ -191,9 +192,12 @@ class Simulation:
                  pack_comps: int = 0, lds_comps: int = 0, use_graph: bool = True,
                  record_timings: bool = False, cost_model: np.ndarray | None = None,
                  epoch_steps: int = 0, stream: int | None = None, solver: int | None = None,
-                 lds_classes: int = 0, plan: tuple | None = None):
+                 lds_classes: int = 0, plan: tuple | None = None,
+                 neuron_cost: np.ndarray | None = None):
         """plan = (lds_bytes_per_cu, n_cu): lay the problem out on the host
-        only (sim_plan_create), for the introspection calls."""
+        only (sim_plan_create), for the introspection calls. neuron_cost:
+        per-neuron costs that learned packing uses in place of a model's
+        predictions."""
         L = lib()
         pr = prob["params"]
         ch = prob["channels"]
@@ -212,6 +216,10 @@ class Simulation:
             self._cm = np.ascontiguousarray(cost_model, np.float32)
             P.cost_model = self._cm.ctypes.data
         P.hip_stream = stream
+        self._nc = None
+        if neuron_cost is not None:
+            self._nc = np.ascontiguousarray(neuron_cost, np.float64)
+            P.neuron_cost = self._nc.ctypes.data
         self.precision = P.precision
         keep = {k: np.ascontiguousarray(prob[k]) for k in (
             "comp_off", "parent", "length_um", "diam_um", "mech", "detector", "iext_nA",

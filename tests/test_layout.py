@@ -307,3 +307,27 @@ def test_contraction_tail_rounds_fit_one_wavefront(S, which):
             while small > 0 and sizes[small - 1] <= 64:
                 small -= 1
             assert 0 <= st <= sizes[small:].sum()
+
+
+def test_learned_packing_takes_given_neuron_costs(S):
+    """Learned packing with per-neuron costs given in place of a model
+    dispatches its best-fit packs in decreasing cost, the largest cost among
+    a pack's neurons; invalid costs are refused."""
+    prob = W.subset(W.make(3), np.arange(600))
+    N = prob["n_comp"].shape[0]
+    rng = np.random.default_rng(11)
+    cost = rng.uniform(1.0, 2.0, N)
+    with plan(S, prob, packing=S.PACK_LEARNED, neuron_cost=cost) as g:
+        assert "learned(given costs)" in g.config
+        pc = [g.pack_info(p)["cost"] for p in range(g.pack_count())]
+        for p in range(g.pack_count()):
+            assert pc[p] == pytest.approx(cost[g.pack_neurons(p)].max())
+        # class by class, the dispatch (workgroup) order is decreasing cost
+        for c in range(3):
+            n_wg = g.class_launch(c)[0]
+            order = [q for w in range(n_wg) for q in g.workgroup_packs(c, w)]
+            cs = [pc[q] for q in order]
+            assert cs == sorted(cs, reverse=True)
+    for bad in (np.zeros(N), np.full(N, np.nan)):
+        with pytest.raises(S.SimError):
+            plan(S, prob, packing=S.PACK_LEARNED, neuron_cost=bad)
