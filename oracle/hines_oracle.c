@@ -639,7 +639,7 @@ int orc_step(orc_sim_t *o, int64_t nsteps)
     for (int64_t s = 0; s < nsteps; ++s) {
         if (o->step + 1 > o->hist_cap) return -1;
         if (o->P.precision == ORC_FP64) {
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel for schedule(dynamic, 8) num_threads(o->nthreads)
             for (int32_t j = 0; j < o->N; ++j) {
                 int tid = 0;
 #ifdef _OPENMP
@@ -648,7 +648,7 @@ int orc_step(orc_sim_t *o, int64_t nsteps)
                 neuron_step_d(o, j, tid);
             }
         } else {
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel for schedule(dynamic, 8) num_threads(o->nthreads)
             for (int32_t j = 0; j < o->N; ++j) {
                 int tid = 0;
 #ifdef _OPENMP
@@ -721,5 +721,15 @@ int orc_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+/* Threads of simulations created from now on (each keeps the count it was
+ * created with, which sizes its per-thread work space). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

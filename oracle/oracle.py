@@ -83,6 +83,8 @@ def lib():
         L.orc_set_input_raster.restype = C.c_int
         L.orc_set_input_raster.argtypes = [P, C.c_int32, C.c_int64, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -258,6 +260,11 @@ class Sim:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the simulations created from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def run(prob: dict, n_steps: int | None = None, precision: int | None = None):

@@ -761,9 +761,18 @@ def test_spike_is_an_upward_threshold_crossing(orc):
 
 def test_threads_do_not_change_results(orc, monkeypatch):
     """Neurons are independent within a step: the parallel neuron loop of the
-    oracle gives bitwise the same network trajectory as any other order."""
+    oracle gives bitwise the same network trajectory with one thread as with
+    several, and as in any other neuron order."""
     prob = W.mini(n_steps=120)
-    v1, s1 = orc.run(prob)
+    n0 = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        v_one, s_one = orc.run(prob)
+        orc.set_num_threads(8)
+        v1, s1 = orc.run(prob)
+    finally:
+        orc.set_num_threads(n0)
+    assert np.array_equal(v_one, v1) and np.array_equal(s_one, s1)
     # permuting neurons must give the same per-neuron results
     perm = np.random.default_rng(5).permutation(prob["n_comp"].shape[0])
     sub = W.subset(prob, perm)
