@@ -243,8 +243,10 @@ int sim_workgroup_packs(const sim_t *sim, int32_t cls, int32_t wg, int32_t *pack
                         int64_t cap, int32_t *n);
 /* Elimination schedule of neuron `neuron` (input id) under
  * SIM_SOLVE_CONTRACT (SIM_ESTATE otherwise): items[4q .. 4q+3] = (k, n1, n2,
- * n1_is_parent) for the q-th eliminated compartment, neuron-local, -1 for an
- * absent neighbour; round r spans items round_off[r] .. round_off[r+1]-1.
+ * flags) for the q-th eliminated compartment, neuron-local, -1 for an
+ * absent neighbour; flags bit 0: n1 is k's current parent, bit 1 (bit 2):
+ * k's coupling to n1 (n2) was made by an earlier elimination rather than
+ * being the off-diagonal. Round r spans items round_off[r] .. round_off[r+1]-1.
  * cap >= 4 * compartments, cap_rounds >= rounds + 1; items == NULL only
  * queries *n_rounds. */
 int sim_contraction_schedule(const sim_t *sim, int32_t neuron, int32_t *items, int64_t cap,

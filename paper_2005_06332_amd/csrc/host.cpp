@@ -127,6 +127,8 @@ void analyse(const int32_t *p, int32_t n, NeuronTopo &t) {
 struct Elim {
     int32_t k, n1, n2;  // neuron-local; n1 / n2 = -1 when absent
     bool n1_parent;     // n1 is k's current parent (else a child, or absent)
+    bool f1, f2;        // the coupling to n1 / n2 was made by an earlier
+                        // elimination (else it is the off-diagonal)
 };
 
 void contraction_schedule(const int32_t *p, int32_t n, std::vector<Elim> &items,
@@ -134,6 +136,7 @@ void contraction_schedule(const int32_t *p, int32_t n, std::vector<Elim> &items,
     items.clear();
     round_off.assign(1, 0);
     std::vector<int32_t> cp(p, p + n), fc(n, -1), ns(n, -1), ps(n, -1), nch(n, 0), stamp(n, 0);
+    std::vector<uint8_t> filled(n, 0);  // coupling to the current parent made by a fill
     auto link = [&](int32_t c, int32_t par) {  // c becomes the first child of par
         cp[c] = par;
         ps[c] = -1;
@@ -178,27 +181,34 @@ void contraction_schedule(const int32_t *p, int32_t n, std::vector<Elim> &items,
                 }
             }
         for (int32_t k : sel) {
-            Elim e{k, -1, -1, false};
+            Elim e{k, -1, -1, false, false, false};
             const int32_t par = cp[k];
             const int32_t c1 = fc[k], c2 = c1 >= 0 ? ns[c1] : -1;
             if (par >= 0) {
                 e.n1 = par;
                 e.n1_parent = true;
                 e.n2 = c1;  // at most one child
+                e.f1 = filled[k];
+                e.f2 = c1 >= 0 && filled[c1];
                 unlink(k);
                 if (c1 >= 0) {
                     unlink(c1);
                     link(c1, par);
+                    filled[c1] = 1;
                 }
             } else if (c1 >= 0) {
                 if (c2 >= 0) {  // a root with two children: c2 hangs off c1
                     e.n1 = c1;
                     e.n2 = c2;
+                    e.f1 = filled[c1];
+                    e.f2 = filled[c2];
                     unlink(c1);
                     unlink(c2);
                     link(c2, c1);
+                    filled[c2] = 1;
                 } else {  // a root with one child: the child becomes the root
                     e.n2 = c1;
+                    e.f2 = filled[c1];
                     unlink(c1);
                 }
             }
@@ -280,7 +290,6 @@ struct Variant {
     int comp_cap = 0;       // count / learned packing: cap on a pack's compartments, 0 = none
     int lds_limit = 64 * 1024;  // bytes of LDS per workgroup
     int sched = SIM_SCHED_PERSISTENT;
-    int prio = 1;  // issue priority step per size class (class c: c * prio, at most 3)
     int nclass = 2;  // LDS size classes in use (1..kClasses)
     int cls_thr = 1;  // class c launches threads << (c * cls_thr) (at most the launch bound)
 
@@ -607,7 +616,7 @@ void analyse_all(sim_t *s) {
                 const Elim &e = items[q];
                 s->citems[b + q] = make_item((uint32_t)e.k, e.n1_parent,
                                              e.n1 < 0 ? kNoNb : (uint32_t)e.n1,
-                                             e.n2 < 0 ? kNoNb : (uint32_t)e.n2);
+                                             e.n2 < 0 ? kNoNb : (uint32_t)e.n2, e.f1, e.f2);
             }
             s->croff.insert(s->croff.end(), roff.begin(), roff.end());
             s->croff0.push_back((int64_t)s->croff.size());
@@ -1014,7 +1023,8 @@ void build_layout(sim_t *s, Variant v) {
                         const uint32_t n2 = (uint32_t)(it >> 32) & 0xFFFFu;
                         cit.push_back(make_item(base + kk, (it >> 15) & 1u,
                                                 n1 == kNoNb ? kNoNb : base + n1,
-                                                n2 == kNoNb ? kNoNb : base + n2));
+                                                n2 == kNoNb ? kNoNb : base + n2, (it >> 49) & 1u,
+                                                (it >> 50) & 1u));
                     }
                 }
                 lvl.push_back((int32_t)(cit.size() - d.it0));
@@ -1363,7 +1373,6 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         a.t0 = t0;
         a.t1 = t1;
         a.scratch_stride = s->scratch_bytes;
-        a.prio = 0;
         return a;
     };
     bool forked = false;
@@ -1376,7 +1385,6 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         }
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
         EpochArgs ac = args(L, c);
-        ac.prio = std::min(3, c * s->var.prio);
         HIPCHK(launch_stamp(ac.ktimer, s->side[c]));
         HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
@@ -1883,7 +1891,8 @@ int sim_contraction_schedule(const sim_t *s, int32_t neuron, int32_t *items, int
         items[4 * q + 0] = (int32_t)(it & 0x7FFFu);
         items[4 * q + 1] = n1 == kNoNb ? -1 : (int32_t)n1;
         items[4 * q + 2] = n2 == kNoNb ? -1 : (int32_t)n2;
-        items[4 * q + 3] = (int32_t)((it >> 15) & 1u);
+        items[4 * q + 3] = (int32_t)((it >> 15) & 1u) | (int32_t)(((it >> 49) & 1u) << 1) |
+                           (int32_t)(((it >> 50) & 1u) << 2);
     }
     const int32_t *ro = s->croff.data() + s->croff0[neuron];
     for (int32_t r = 0; r <= nr; ++r) round_off[r] = ro[r];

@@ -69,13 +69,15 @@ constexpr int kWave = 64;
 
 // Contraction solver item, one per compartment of a pack: bits 0..14 the
 // eliminated compartment k, bit 15 set when n1 is k's current parent, bits
-// 16..31 n1, bits 32..47 n2 (pack-local; kNoNb when absent). Items are
-// stored by round; round r of a pack spans items rof[r] .. rof[r+1]-1.
+// 16..31 n1, bits 32..47 n2 (pack-local; kNoNb when absent), bit 49 (50) set
+// when the coupling to n1 (n2) was made by an earlier elimination of the
+// step (it is then in the working slot, else it is the off-diagonal). Items
+// are stored by round; round r of a pack spans items rof[r] .. rof[r+1]-1.
 constexpr uint32_t kNoNb = 0xFFFF;
 __host__ __device__ inline uint64_t make_item(uint32_t k, bool n1_parent, uint32_t n1,
-                                              uint32_t n2) {
+                                              uint32_t n2, bool f1 = false, bool f2 = false) {
     return (uint64_t)(k & 0x7FFFu) | (n1_parent ? 0x8000ull : 0ull) | ((uint64_t)n1 << 16) |
-           ((uint64_t)n2 << 32);
+           ((uint64_t)n2 << 32) | (f1 ? (1ull << 49) : 0ull) | (f2 ? (1ull << 50) : 0ull);
 }
 
 // Everything the epoch kernel reads or writes. T is the gating precision.
@@ -133,7 +135,6 @@ struct EpochArgs {
     // [1] latest workgroup end, [2] finished workgroups of the running
     // launch, [4] summed launch spans, [5] launches
     uint64_t *ktimer;
-    int32_t prio;         // wave issue priority 0..3 (larger packs: higher)
 };
 
 // Bytes of per-pack state for a pack of n compartments, s synapses and k

@@ -580,9 +580,10 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // current neighbours n1, n2 (couplings a1, a2) is one step of Gaussian
 // elimination: each neighbour's diagonal loses a^2/d_k and its right-hand
 // side a r_k/d_k; when both exist, n2 is linked to n1 with the coupling
-// -a1 a2/d_k. The V slot, free once the matrix is assembled, holds every
-// compartment's coupling to its current parent (W, a copy of the
-// off-diagonal at first). What k's back substitution needs replaces what k no
+// -a1 a2/d_k. The V slot, free once the matrix is assembled, takes the
+// couplings made by these fills (W); a coupling no elimination has made yet
+// is still the off-diagonal, and the item says which of the two holds each
+// of k's couplings. What k's back substitution needs replaces what k no
 // longer needs: h = r_k/d_k into R[k], g1 = a1/d_k into W[k], g2 = a2/d_k
 // into D[k]. A round's eliminations are at least three apart in the current
 // tree, so each survivor is written by one lane at most.
@@ -593,14 +594,16 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // stands in for k: its reads are k's values and its writes put them back
 // unchanged, before k's own results are written.
 __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
-                                              double *__restrict__ W, const uint64_t it) {
+                                              double *__restrict__ W,
+                                              const double *__restrict__ Eo, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
     const bool up = (it >> 15) & 1u;
     const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
     const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
     const int i1 = h1 ? (int)n1 : k, i2 = h2 ? (int)n2 : k;
+    const double *B1 = ((it >> 49) & 1u) ? W : Eo, *B2 = ((it >> 50) & 1u) ? W : Eo;
     const double dk = D[k], rk = R[k];
-    const double w1 = W[up ? k : i1], w2 = W[i2];
+    const double w1 = B1[up ? k : i1], w2 = B2[i2];
     const double d1 = D[i1], r1 = R[i1], d2 = D[i2], r2 = R[i2];
     const double a1 = h1 ? w1 : 0.0, a2 = h2 ? w2 : 0.0;
     const double y = rcp_nr(dk);
@@ -932,9 +935,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         if constexpr (kContract) {
             // ---- C': contraction rounds, then back substitution ------------
             // (V^n is no longer needed: detection keeps its own copy, so the
-            // V slot takes the working couplings)
-            for (int i = tid; i < n; i += NT) V[i] = Eo[i];
-            __syncthreads();
+            // V slot takes the couplings the eliminations make)
             // every thread takes items of each round, a workgroup barrier
             // between rounds; the items stay in global memory (L2), and each
             // thread reads its first item of the next round before working on
@@ -958,9 +959,9 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     // round's work and barrier
                     const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
                     const uint64_t nxt = item(hi + tid, hi2);
-                    if (lo + tid < hi) contract_elim(D, R, V, cur);
+                    if (lo + tid < hi) contract_elim(D, R, V, Eo, cur);
                     for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
-                        contract_elim(D, R, V, cit[q2]);
+                        contract_elim(D, R, V, Eo, cit[q2]);
                     __syncthreads();
                     lo = hi;
                     hi = hi2;
@@ -982,7 +983,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     for (int r = nw; r < nr; ++r) {
                         const int hi2 = (r + 1 < nr) ? rofw(r + 2) : hi;
                         const uint64_t nxt = tail_item(hi + tid);
-                        if (lo + tid < hi) contract_elim(D, R, V, cur);
+                        if (lo + tid < hi) contract_elim(D, R, V, Eo, cur);
                         wave_lds_sync();
                         lo = hi;
                         hi = hi2;
@@ -1148,14 +1149,6 @@ template <typename T, int kSolve>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
     k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
-    // the launches of the larger packs hold the epoch's critical path: their
-    // waves get issue priority over those of the small-pack launch
-    if (a.prio == 1)
-        __builtin_amdgcn_s_setprio(1);
-    else if (a.prio == 2)
-        __builtin_amdgcn_s_setprio(2);
-    else if (a.prio >= 3)
-        __builtin_amdgcn_s_setprio(3);
     const int64_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
     if (a.ktimer && threadIdx.x == 0)
         atomicMin((unsigned long long *)&a.ktimer[0], (unsigned long long)wall_clock64());

@@ -356,7 +356,9 @@ class Simulation:
         return out
 
     def contraction_schedule(self, neuron: int, n_comp: int):
-        """(items [n_comp, 4] = (k, n1, n2, n1_is_parent), round offsets)."""
+        """(items [n_comp, 4] = (k, n1, n2, flags), round offsets); flags bit 0:
+        n1 is k's parent, bits 1 and 2: k's coupling to n1 / n2 was made by an
+        earlier elimination."""
         nr = C.c_int32(0)
         _check(lib().sim_contraction_schedule(self._h, int(neuron), None, 0, None, 0,
                                               C.byref(nr)), self._h)

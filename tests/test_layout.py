@@ -185,14 +185,18 @@ def contracted_neighbours(parent_cur, children_cur, k):
 
 def execute_schedule(items, ro, p, e, d, r):
     """The elimination the schedule describes, in numpy (test-side), then back
-    substitution in reverse round order."""
+    substitution in reverse round order. As in the kernel, a coupling is read
+    from the slot the fills write (EW, which starts with no valid entry) when
+    the item flags it as made by an earlier elimination, else from the
+    off-diagonal e."""
     n = len(p)
-    D, R, V, EW = d.copy(), r.copy(), np.zeros(n), e.copy()
+    D, R, V, EW = d.copy(), r.copy(), np.zeros(n), np.full(n, np.nan)
     for q in range(len(items)):
-        k, n1, n2, up = items[q]
+        k, n1, n2, fl = items[q]
+        up = fl & 1
         y = 1.0 / D[k]
-        a1 = (EW[k] if up else EW[n1]) if n1 >= 0 else 0.0
-        a2 = EW[n2] if n2 >= 0 else 0.0
+        a1 = ((EW if fl & 2 else e)[k if up else n1]) if n1 >= 0 else 0.0
+        a2 = (EW if fl & 4 else e)[n2] if n2 >= 0 else 0.0
         if n1 >= 0:
             D[n1] -= a1 * a1 * y
             R[n1] -= a1 * R[k] * y
@@ -228,6 +232,7 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
             assert sorted(items[:, 0].tolist()) == list(range(n))
             assert ro[0] == 0 and ro[-1] == n and np.all(np.diff(ro) > 0)
             # replay the contraction on the tree and check each round
+            made = np.zeros(n, bool)  # coupling to the current parent made by a fill
             par = p.copy()
             ch = [set() for _ in range(n)]
             for i in range(1, n):
@@ -235,11 +240,17 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
             for rr in range(len(ro) - 1):
                 closed = set()
                 for q in range(ro[rr], ro[rr + 1]):
-                    k, n1, n2, up = (int(x) for x in items[q])
+                    k, n1, n2, fl = (int(x) for x in items[q])
+                    up = fl & 1
                     nb = contracted_neighbours(par, ch, k)
                     assert len(nb) <= 2
                     assert nb == {x for x in (n1, n2) if x >= 0}
                     assert (up == 1) == (n1 >= 0 and par[k] == n1)
+                    # which couplings are fills, which the off-diagonal
+                    if n1 >= 0:
+                        assert bool(fl & 2) == bool(made[k] if up else made[n1])
+                    if n2 >= 0:
+                        assert bool(fl & 4) == bool(made[n2])
                     ball = nb | {k}
                     assert not (ball & closed), "round members closer than 3"
                     closed |= ball
@@ -252,6 +263,7 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
                     if n1 >= 0 and n2 >= 0:  # n2 hangs off n1 from now on
                         par[n2] = n1
                         ch[n1].add(n2)
+                        made[n2] = True
                     ch[k] = set()
                     par[k] = -2
             # the elimination solves a random symmetric diagonally dominant
