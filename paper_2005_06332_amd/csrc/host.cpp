@@ -282,6 +282,7 @@ struct Launch {
     int threads = 256;
     size_t lds = 256;
     int32_t off0 = 0, list0 = 0;
+    bool resident = false;  // every pack in LDS with every compartment register-resident
 };
 
 struct Variant {
@@ -349,7 +350,7 @@ struct sim {
 
     // layout: the host arrays build_layout produces, held until uploaded
     struct HostLayout {
-        std::vector<uint32_t> topo;
+        std::vector<uint32_t> topo, cnb;
         std::vector<int32_t> lparent, nid, ndet, lvl, spre, sdel;
         std::vector<double> len, dia, w64, iext64;
         std::vector<int64_t> ncomp0;
@@ -382,7 +383,7 @@ struct sim {
     DBuf<int32_t> d_wg_off, d_wg_list, d_spre, d_sdelay, d_nid, d_ndet, d_lvl, d_lparent;
     DBuf<double> d_V, d_cdt, d_e, d_len, d_diam, d_w64, d_iext64, d_q;
     DBuf<char> d_gm, d_gh, d_gn, d_af, d_sg, d_sw, d_niext, d_scratch;
-    DBuf<uint32_t> d_topo;
+    DBuf<uint32_t> d_topo, d_cnb;
     DBuf<uint16_t> d_scomp, d_sseg, d_chl;
     DBuf<Branch> d_br;
     DBuf<uint16_t> d_fw;
@@ -812,6 +813,7 @@ void build_layout(sim_t *s, Variant v) {
 
     s->hl = sim_t::HostLayout{};
     auto &topo = s->hl.topo;
+    auto &cnb = s->hl.cnb;  // children words (make_children)
     auto &lparent = s->hl.lparent, &nid = s->hl.nid, &ndet = s->hl.ndet, &lvl = s->hl.lvl;
     auto &len = s->hl.len, &dia = s->hl.dia, &w64 = s->hl.w64, &iext64 = s->hl.iext64;
     auto &ncomp0 = s->hl.ncomp0;
@@ -824,6 +826,7 @@ void build_layout(sim_t *s, Variant v) {
     // per-pack branch scratch (pack-local branch index = br_base + local)
     std::vector<int32_t> tb0, tb1, tpar, tch_off, tch, pos, child0;
     topo.reserve(s->C);
+    cnb.reserve(s->C);
     lparent.reserve(s->C);
     len.reserve(s->C);
     dia.reserve(s->C);
@@ -875,11 +878,21 @@ void build_layout(sim_t *s, Variant v) {
             // branch-end marker per local compartment
             std::vector<int32_t> end_branch(n, -1);
             for (int32_t bb = 0; bb < nb; ++bb) end_branch[t.b1[bb]] = bb;
+            // children of each compartment, ascending (parent[i] < i)
+            std::vector<int32_t> nch_of(n, 0), ch1(n, -1), ch2(n, -1);
+            for (int32_t i = 1; i < n; ++i) {
+                const int32_t pp = s->parent[b + i];
+                if (nch_of[pp] == 0) ch1[pp] = i; else if (nch_of[pp] == 1) ch2[pp] = i;
+                nch_of[pp]++;
+            }
             for (int32_t i = 0; i < n; ++i) {
                 const bool root = i == 0;
                 const uint32_t par = root ? (uint32_t)k : (uint32_t)(comp_base + s->parent[b + i]);
                 const uint32_t bid = end_branch[i] >= 0 ? (uint32_t)(br_base + end_branch[i]) : kNone;
                 topo.push_back(make_topo(par, s->mech[b + i] != 0, bid, root));
+                cnb.push_back(nch_of[i] > 2 ? kManyChildren
+                                            : make_children(ch1[i] >= 0 ? comp_base + ch1[i] : kNoNb,
+                                                            ch2[i] >= 0 ? comp_base + ch2[i] : kNoNb));
                 lparent.push_back(s->parent[b + i]);
                 len.push_back(s->length[b + i]);
                 dia.push_back(s->diam[b + i]);
@@ -1109,6 +1122,13 @@ void build_layout(sim_t *s, Variant v) {
         for (int p = 0; p < npk; ++p)
             if (pclass[p] == c) mine.push_back(p);
         const int np = (int)mine.size();
+        // the resident-only kernel applies when every pack of the class keeps
+        // its state in LDS and each thread's compartments fit its register
+        // slots (FP32 gating, contraction solver)
+        L.resident = np > 0 && s->tsize == 4 && s->solver == SIM_SOLVE_CONTRACT;
+        for (int p : mine)
+            if (s->packs[p].global_mem || s->packs[p].ncomp > kResident * L.threads)
+                L.resident = false;
         if (np == 0) {
             L.n_wg = 0;
             s->wg_off.push_back(0);
@@ -1162,6 +1182,7 @@ void upload_layout(sim_t *s) {
     s->d_wg_off.upload(s->wg_off);
     s->d_wg_list.upload(s->wg_list);
     s->d_topo.upload(h.topo);
+    s->d_cnb.upload(h.cnb);
     s->d_lparent.upload(h.lparent);
     s->d_len.upload(h.len);
     s->d_diam.upload(h.dia);
@@ -1252,6 +1273,7 @@ EpochArgs make_args(sim_t *s) {
     a.gh = s->d_gh.p;
     a.gn = s->d_gn.p;
     a.topo = s->d_topo.p;
+    a.cnb = s->d_cnb.p;
     a.cdt = s->d_cdt.p;
     a.e = s->d_e.p;
     a.af = s->d_af.p;
@@ -1289,6 +1311,11 @@ EpochArgs make_args(sim_t *s) {
     a.e_syn = s->P.e_syn_mV;
     a.dt = s->P.dt_ms;
     a.q = s->q;
+    {
+        const double dc[11] = {a.gnabar, a.gkbar, a.gl,    a.ena, a.ek, a.el,
+                               a.g_pas,  a.e_pas, a.e_syn, a.dt,  a.q};
+        for (int k = 0; k < 11; ++k) a.fch[k] = (float)dc[k];
+    }
     a.pack_time = s->P.record_timings ? s->d_ptime.p : nullptr;
     return a;
 }
@@ -1386,14 +1413,15 @@ void launch_range(sim_t *s, int64_t epoch, int t0, int t1, bool use_ptr) {
         HIPCHK(hipStreamWaitEvent(s->side[c], s->ev_fork, 0));
         EpochArgs ac = args(L, c);
         HIPCHK(launch_stamp(ac.ktimer, s->side[c]));
-        HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, s->side[c]));
+        HIPCHK(launch_epoch(ac, pr, s->solver, L.n_wg, L.threads, L.lds, L.resident, s->side[c]));
         HIPCHK(hipEventRecord(s->ev_join[c], s->side[c]));
     }
     const Launch &S0 = s->launch[0];
     if (S0.n_wg > 0) {
         const EpochArgs a0 = args(S0, 0);
         HIPCHK(launch_stamp(a0.ktimer, s->stream));
-        HIPCHK(launch_epoch(a0, pr, s->solver, S0.n_wg, S0.threads, S0.lds, s->stream));
+        HIPCHK(launch_epoch(a0, pr, s->solver, S0.n_wg, S0.threads, S0.lds, S0.resident,
+                                 s->stream));
     }
     for (int c = 1; c < kClasses; ++c)
         if (s->launch[c].n_wg > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join[c], 0));
@@ -2127,7 +2155,7 @@ void sim_destroy(sim_t *s) {
     fr(s->d_nid); fr(s->d_ndet); fr(s->d_lvl); fr(s->d_lparent); fr(s->d_V); fr(s->d_cdt);
     fr(s->d_e); fr(s->d_len); fr(s->d_diam); fr(s->d_w64);
     fr(s->d_iext64); fr(s->d_q); fr(s->d_gm); fr(s->d_gh); fr(s->d_gn); fr(s->d_af);
-    fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_scomp);
+    fr(s->d_sg); fr(s->d_sw); fr(s->d_niext); fr(s->d_scratch); fr(s->d_topo); fr(s->d_cnb); fr(s->d_scomp);
     fr(s->d_sseg); fr(s->d_chl); fr(s->d_fw); fr(s->d_cit); fr(s->d_br); fr(s->d_ncomp0); fr(s->d_epoch);
     fr(s->d_ring); fr(s->d_ptime); fr(s->d_ktimer);
     for (int k = 0; k < 2; ++k) {

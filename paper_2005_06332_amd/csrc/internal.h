@@ -29,6 +29,15 @@ __host__ __device__ inline uint32_t make_topo(uint32_t parent_or_neuron, bool hh
            ((branch & 0x7FFFu) << 16) | (root ? 0x80000000u : 0u);
 }
 
+// Children word of a compartment: its first two children (pack-local, in
+// ascending order; kNoNb when absent) as c1 | c2 << 16, or kManyChildren
+// when it has more than two (their bases are then read from the branch
+// record the topology word names).
+constexpr uint32_t kManyChildren = 0xFFFFFFFEu;
+__host__ __device__ inline uint32_t make_children(uint32_t c1, uint32_t c2) {
+    return (c1 & 0xFFFFu) | ((c2 & 0xFFFFu) << 16);
+}
+
 // A branch: a maximal run b0..b1 of consecutive compartments where each one
 // is the only child of the previous. Branch records of a pack are stored in
 // backward-sweep order (by height, longest chains first within a level), and
@@ -89,6 +98,7 @@ struct EpochArgs {
     double *V;
     void *gm, *gh, *gn;
     const uint32_t *topo;
+    const uint32_t *cnb;  // children words
     const double *cdt;  // C/dt (uS)
     const double *e;    // off-diagonal -theta*G (G = coupling to parent, uS), 0 at roots
     const void *af;     // area factor (T)
@@ -128,6 +138,7 @@ struct EpochArgs {
     double ginv;       // -1/theta (exact: theta is 1/2 or 1)
     double v_thresh;
     double gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
+    float fch[11];     // the same eleven, rounded to float (FP32 gating)
     // timing
     uint64_t *pack_time;  // accumulated ns per pack, or null
     // launch timer of this size class (device clock ticks): [0] start (set
@@ -183,8 +194,11 @@ struct SetupArgs {
 hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s);
 // solver: 0 = exact operation order of the elimination, 1 = division-free
 // homogeneous form, 2 = tree contraction
+// resident: the launch's packs all keep their state in LDS and have at most
+// kResident compartments per thread (FP32 gating, contraction solver only),
+// which selects a kernel without the global-state and non-resident paths
 hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg, int threads,
-                        size_t lds_bytes, hipStream_t s);
+                        size_t lds_bytes, bool resident, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_advance(int64_t *epoch, hipStream_t s);
 hipError_t launch_stamp(uint64_t *timer, hipStream_t s);
@@ -196,6 +210,9 @@ hipError_t set_epoch_lds_limit(int bytes);
 constexpr int64_t kNoAllocScratchBytes = (int64_t)64 << 20;
 constexpr int kMaxDevices = 64;
 hipError_t noalloc_scratch(void **ptr);
+// Compartments per thread whose gates and constants the epoch kernel keeps in
+// registers for a whole epoch (FP32 gating, contraction solver).
+constexpr int kResident = 4;
 // Largest epoch-kernel workgroup (launch bounds): double precision needs
 // more registers per lane.
 constexpr int kMaxThreadsF32 = 1024;

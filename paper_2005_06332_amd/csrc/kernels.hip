@@ -648,11 +648,36 @@ struct Consts {
     double omt, vth, ginv;
 };
 
+// A copy of a wave-uniform value in a scalar register of its own (the
+// compiler cannot see through the move).
+__device__ __forceinline__ double sreg(double x) {
+    double y;
+    asm volatile("s_mov_b64 %0, %1" : "=s"(y) : "s"(x));
+    return y;
+}
+__device__ __forceinline__ float sreg(float x) {
+    float y;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(y) : "s"(x));
+    return y;
+}
+
 // Channel constants of the membrane model, in the gating precision.
 template <typename T>
 struct Chan {
     T gnabar, gkbar, gl, ena, ek, el, g_pas, e_pas, e_syn, dt, q;
 };
+template <typename T>
+__device__ __forceinline__ Chan<T> chan_consts(const EpochArgs &a) {
+    if constexpr (sizeof(T) == 4) {
+        const float *f = a.fch;
+        return Chan<T>{sreg(f[0]), sreg(f[1]), sreg(f[2]), sreg(f[3]), sreg(f[4]),  sreg(f[5]),
+                       sreg(f[6]), sreg(f[7]), sreg(f[8]), sreg(f[9]), sreg(f[10])};
+    } else {
+        return Chan<T>{sreg(a.gnabar), sreg(a.gkbar), sreg(a.gl),    sreg(a.ena),
+                       sreg(a.ek),     sreg(a.el),    sreg(a.g_pas), sreg(a.e_pas),
+                       sreg(a.e_syn),  sreg(a.dt),    sreg(a.q)};
+    }
+}
 
 // Membrane conductance and source of one compartment from its gates, per
 // unit of the compartment's own area factor: P = a*g_ion, Q = a*J_ion
@@ -721,6 +746,53 @@ __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const d
     R[i] = (cdt * v + (double)J) + c.omt * ax;
 }
 
+// Phase B with the compartment's children word (chw, see make_children):
+// the same operations in the same order as assemble(), but every operand is
+// read at once, with no dependent read of a branch record or child list
+// (an absent parent or child reads the compartment's own slots and its term
+// is not applied). A compartment with more than two children takes
+// assemble()'s path.
+template <typename T>
+__device__ __forceinline__ void assemble_cw(const int i, const uint32_t tp, const uint32_t chw,
+                                            const double cdt, const double *__restrict__ V,
+                                            double *__restrict__ R, double *__restrict__ D,
+                                            const double *__restrict__ Eo,
+                                            const Branch *__restrict__ br,
+                                            const uint16_t *__restrict__ chl,
+                                            const double *__restrict__ IX, const Consts c) {
+    if (chw == kManyChildren) {
+        assemble<T>(i, tp, cdt, V, R, D, Eo, br, chl, IX, c);
+        return;
+    }
+    const bool root = topo_root(tp);
+    const int pi = (int)topo_parent(tp);  // the neuron's index in the pack at a root
+    const uint32_t u1 = chw & 0xFFFFu, u2 = chw >> 16;
+    const bool h1 = u1 != kNoNb, h2 = u2 != kNoNb;
+    const int c1 = h1 ? (int)u1 : i, c2 = h2 ? (int)u2 : i;
+    const double v = V[i];
+    const T gmem = *(const T *)&D[i];
+    const T jm = *(const T *)&R[i];
+    const T ix = *(const T *)&IX[pi];
+    const double ei = Eo[i], vp = V[pi];
+    const double e1 = Eo[c1], v1 = V[c1], e2 = Eo[c2], v2 = V[c2];
+    const T J = jm + (root ? ix : T(0));
+    double ax = 0.0, d = cdt;
+    if (!root) {
+        ax = (ei * c.ginv) * (vp - v);
+        d = d - ei;
+    }
+    if (h1) {
+        ax = ax - (e1 * c.ginv) * (v - v1);
+        d = d - e1;
+    }
+    if (h2) {
+        ax = ax - (e2 * c.ginv) * (v - v2);
+        d = d - e2;
+    }
+    D[i] = d + (double)gmem;
+    R[i] = (cdt * v + (double)J) + c.omt * ax;
+}
+
 template <typename T>
 __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x, const T dt) {
     const T v = (T)v64;
@@ -770,8 +842,8 @@ __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk
 // for j < kResident. The rest of a larger pack reads them from global memory
 // each step, as do the level-sweep solvers (whose sweeps already hold most
 // of the register budget) and FP64 gating (whose gates take twice the
-// registers).
-constexpr int kResident = 4;
+// registers). A launch whose packs all fit the resident slots (kRes) leaves
+// those paths out, which frees the scalar registers they held.
 
 // One pack through steps [t0, t1) of an epoch. V, R, D and the off-diagonal
 // live at `base` (LDS, or a global scratch slice for packs larger than any
@@ -783,7 +855,7 @@ constexpr int kResident = 4;
 // In the sweeps the branches of a level go to consecutive lanes (sorted by
 // length on the host), so one wave instruction advances as many chains as
 // the level has branches.
-template <typename T, int kSolve>
+template <typename T, int kSolve, bool kRes>
 __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk, char *smem,
                                          char *base, int64_t epoch) {
     constexpr bool kFast = kSolve == 1;
@@ -833,25 +905,30 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const T *af = (const T *)a.af + c0;
     const double *cdtp = a.cdt + c0;
     const uint32_t *topo = a.topo + c0;
+    const uint32_t *cnbp = a.cnb + c0;
     const T *niext = (const T *)a.niext;
     double *__restrict__ IX = st.IX;
     const Branch *br = tb.br;
     const uint16_t *chl = tb.chl;
     const int32_t *lvl = tb.lvl;
 
-    const Chan<T> ch{(T)a.gnabar, (T)a.gkbar, (T)a.gl,    (T)a.ena, (T)a.ek, (T)a.el,
-                     (T)a.g_pas,  (T)a.e_pas, (T)a.e_syn, (T)a.dt,  (T)a.q};
+    // Each constant is copied into a scalar register of its own: otherwise
+    // the compiler keeps the wide scalar loads they came from (eight doubles
+    // in one register tuple) alive across the step loop, and when that tuple
+    // spills it reloads all of it wherever one constant is used.
+    const Chan<T> ch = chan_consts<T>(a);
+    const Consts cs{sreg(a.omt), sreg(a.v_thresh), sreg(a.ginv)};
     const T e_syn = ch.e_syn, dt = ch.dt, q = ch.q;
-    const Consts cs{a.omt, a.v_thresh, a.ginv};
     const int t0 = a.t0, t1 = a.t1;
 
     // resident compartments: tid + j*NT for j < KR; the others from i0 on
     constexpr int KR = (sizeof(T) == 4 && kContract) ? kResident : 0;
+    static_assert(!kRes || KR > 0, "the resident-only kernel needs register slots");
     constexpr int KA = KR > 0 ? KR : 1;
     const int i0 = tid + KR * NT;
     T rm[KA], rh[KA], rx[KA], raf[KA];
     double rcdt[KA];
-    uint32_t rtp[KA];
+    uint32_t rtp[KA], rcw[KA];
 
     // ---- load state -------------------------------------------------------
     for (int i = tid; i < n; i += NT) {
@@ -868,11 +945,13 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             raf[j] = af[i];
             rcdt[j] = cdtp[i];
             rtp[j] = topo[i];
+            rcw[j] = cnbp[i];
             membrane<T>(rtp[j], raf[j], rm[j], rh[j], rx[j], ch, *(T *)&D[i], *(T *)&R[i]);
         }
     }
-    for (int i = i0; i < n; i += NT)
-        membrane<T>(topo[i], af[i], gm[i], gh[i], gn[i], ch, *(T *)&D[i], *(T *)&R[i]);
+    if constexpr (!kRes)
+        for (int i = i0; i < n; i += NT)
+            membrane<T>(topo[i], af[i], gm[i], gh[i], gn[i], ch, *(T *)&D[i], *(T *)&R[i]);
     for (int k = tid; k < ns; k += NT) {
         SG[k] = ((const T *)a.sg)[s0 + k];
         st.SM[k] = event_mask(a.ring, a.ring_rows, a.n_neurons, a.E, epoch, a.spre[s0 + k],
@@ -896,7 +975,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         int tl = tid;
         asm volatile("" : "+v"(tl));
 #pragma unroll
-        for (int j = 0; j < KR; ++j) asm volatile("" : "+v"(rtp[j]));
+        for (int j = 0; j < KR; ++j) asm volatile("" : "+v"(rtp[j]), "+v"(rcw[j]));
         // ---- A: delivery; each compartment's synaptic conductance joins its
         // membrane terms (P += g, Q += g E_syn) ------------------------------
         for (int k = tid; k < ns; k += NT) {
@@ -923,12 +1002,14 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 #pragma unroll
         for (int j = 0; j < KR; ++j) {
             const int i = tl + j * NT;
-            if (i < n) assemble<T>(i, rtp[j], rcdt[j], V, R, D, Eo, br, chl, IX, cs);
+            if (i < n) assemble_cw<T>(i, rtp[j], rcw[j], rcdt[j], V, R, D, Eo, br, chl, IX, cs);
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (!kRes) {
 #pragma unroll 2
-        for (int i = i0; i < n; i += NT)
-            assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, IX, cs);
+            for (int i = i0; i < n; i += NT)
+                assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, IX, cs);
+        }
         __syncthreads();
         MMH_PHASE(2);
 
@@ -1092,17 +1173,19 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             // would hold several sets of rate temporaries live at once
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (!kRes) {
 #pragma unroll 1
-        for (int i = i0; i < n; i += NT) {
-            const uint32_t tp = topo[i];
-            T m = gm[i], h = gh[i], x = gn[i];
-            if (topo_hh(tp)) {
-                gates_update<T>(V[i], m, h, x, dt);
-                gm[i] = m;
-                gh[i] = h;
-                gn[i] = x;
+            for (int i = i0; i < n; i += NT) {
+                const uint32_t tp = topo[i];
+                T m = gm[i], h = gh[i], x = gn[i];
+                if (topo_hh(tp)) {
+                    gates_update<T>(V[i], m, h, x, dt);
+                    gm[i] = m;
+                    gh[i] = h;
+                    gn[i] = x;
+                }
+                if (more) membrane<T>(tp, af[i], m, h, x, ch, *(T *)&D[i], *(T *)&R[i]);
             }
-            if (more) membrane<T>(tp, af[i], m, h, x, ch, *(T *)&D[i], *(T *)&R[i]);
         }
         for (int k = tid; k < nn; k += NT) {
             const double vn = V[st.ND[2 * k]];
@@ -1145,7 +1228,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
 #endif
 }
 
-template <typename T, int kSolve>
+template <typename T, int kSolve, bool kRes = false>
 __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF32)
     k_epoch(EpochArgs a) {
     extern __shared__ __align__(16) char smem[];
@@ -1161,11 +1244,12 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreadsF64 : kMaxThreadsF
         // two call sites, so that in the common one the state pointer is
         // visibly derived from the shared array and its accesses compile to
         // LDS instructions rather than generic (flat) ones
-        if (pk.global_mem)
-            run_pack<T, kSolve>(a, pk, smem,
-                                a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride, epoch);
+        if (!kRes && pk.global_mem)
+            run_pack<T, kSolve, kRes>(a, pk, smem,
+                                      a.scratch + (int64_t)(pk.global_mem - 1) * a.scratch_stride,
+                                      epoch);
         else
-            run_pack<T, kSolve>(a, pk, smem, smem + pk.tbytes, epoch);
+            run_pack<T, kSolve, kRes>(a, pk, smem, smem + pk.tbytes, epoch);
         __syncthreads();
         if (a.pack_time && threadIdx.x == 0)
             atomicAdd((unsigned long long *)&a.pack_time[pid],
@@ -1230,7 +1314,7 @@ hipError_t launch_setup(const SetupArgs &a, int precision, hipStream_t s) {
 }
 
 hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg, int threads,
-                        size_t lds_bytes, hipStream_t s) {
+                        size_t lds_bytes, bool resident, hipStream_t s) {
     const dim3 g(n_wg), b(threads);
     if (precision == 0) {
         if (solver == 0)
@@ -1244,6 +1328,8 @@ hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg,
             hipLaunchKernelGGL((k_epoch<float, 0>), g, b, lds_bytes, s, a);
         else if (solver == 1)
             hipLaunchKernelGGL((k_epoch<float, 1>), g, b, lds_bytes, s, a);
+        else if (resident)
+            hipLaunchKernelGGL((k_epoch<float, 2, true>), g, b, lds_bytes, s, a);
         else
             hipLaunchKernelGGL((k_epoch<float, 2>), g, b, lds_bytes, s, a);
     }
@@ -1253,7 +1339,8 @@ hipError_t launch_epoch(const EpochArgs &a, int precision, int solver, int n_wg,
 hipError_t set_epoch_lds_limit(int bytes) {
     const void *fns[] = {(const void *)k_epoch<double, 0>, (const void *)k_epoch<double, 1>,
                          (const void *)k_epoch<double, 2>, (const void *)k_epoch<float, 0>,
-                         (const void *)k_epoch<float, 1>, (const void *)k_epoch<float, 2>};
+                         (const void *)k_epoch<float, 1>, (const void *)k_epoch<float, 2>,
+                         (const void *)k_epoch<float, 2, true>};
     for (const void *f : fns) {
         const hipError_t e =
             hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
