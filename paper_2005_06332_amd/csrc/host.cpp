@@ -293,6 +293,10 @@ struct Variant {
     int sched = SIM_SCHED_PERSISTENT;
     int nclass = 2;  // LDS size classes in use (1..kClasses)
     int cls_thr = 1;  // class c launches threads << (c * cls_thr) (at most the launch bound)
+    bool res_cap = false;  // count / learned packing: no pack of class c holds more
+                           // compartments than its threads' register slots
+                           // (kResident per thread), so its launch keeps every
+                           // compartment's gates and constants in registers
 
 };
 
@@ -727,6 +731,11 @@ void build_layout(sim_t *s, Variant v) {
 #define MMH_TAIL_SHARE 8
 #endif
         const int64_t tail_share = MMH_TAIL_SHARE;
+        const int thr_max = s->tsize == 8 ? kMaxThreadsF64 : kMaxThreadsF32;
+        auto res_cap_of = [&](int cls) -> int64_t {
+            return v.res_cap ? (int64_t)kResident * std::min(v.threads << (cls * v.cls_thr), thr_max)
+                             : INT64_MAX;
+        };
         auto bytes_of = [&](int64_t n, int64_t ns, int32_t nbr, int32_t nch, int32_t maxh,
                             int32_t maxd, int32_t maxr, int64_t k) -> int64_t {
             const int64_t nlev = (int64_t)maxh + maxd + 4;
@@ -753,7 +762,7 @@ void build_layout(sim_t *s, Variant v) {
                  ++it, ++tries) {
                 const Bin &B = bins[it->second];
                 if (B.members.size() >= 1024 || B.n + n > 32766 || B.nbr + nb > 32766 ||
-                    (v.comp_cap > 0 && B.n + n > v.comp_cap))
+                    (v.comp_cap > 0 && B.n + n > v.comp_cap) || B.n + n > res_cap_of(B.cls))
                     continue;
                 const int64_t with = bytes_of(B.n + n, B.ns + ns, B.nbr + nb, B.nch + nb - 1,
                                               std::max(B.maxh, t.max_height),
@@ -766,7 +775,8 @@ void build_layout(sim_t *s, Variant v) {
             }
             if (chosen < 0) {
                 Bin B;
-                while (B.cls + 1 < ncls && alone > cls_budget[B.cls]) ++B.cls;
+                while (B.cls + 1 < ncls && (alone > cls_budget[B.cls] || n > res_cap_of(B.cls)))
+                    ++B.cls;
                 bins.push_back(B);
                 where.push_back(open.end());
                 chosen = (int32_t)bins.size() - 1;
@@ -1062,7 +1072,13 @@ void build_layout(sim_t *s, Variant v) {
         const int64_t bytes = state_bytes(s, d.ncomp, d.nsyn, d.nneur);
         if (d.tbytes > s->max_lds) throw fail(SIM_EINVAL, "pack topology tables exceed LDS");
         int c = 0;
-        while (c + 1 < ncls && d.tbytes + bytes > cls_budget[c]) ++c;
+        while (c + 1 < ncls &&
+               (d.tbytes + bytes > cls_budget[c] ||
+                (v.res_cap && s->P.packing != SIM_PACK_PLAIN &&
+                 d.ncomp > (int64_t)kResident *
+                               std::min(v.threads << (c * v.cls_thr),
+                                        s->tsize == 8 ? kMaxThreadsF64 : kMaxThreadsF32))))
+            ++c;
         d.global_mem = d.tbytes + bytes <= cls_budget[c] ? 0 : 1;
         if (s->solver == SIM_SOLVE_CONTRACT && d.nrnd > 0) {
             // stage the single-wavefront tail of the schedule in LDS, as much
@@ -1669,6 +1685,25 @@ void autotune(sim_t *s, Variant base) {
     {
         Variant v = base;
         v.sched = SIM_SCHED_PERSISTENT;
+        cand.push_back(v);
+    }
+    if (s->tsize == 4 && s->solver == SIM_SOLVE_CONTRACT) {
+        // packs capped at the register slots of their class's threads, so
+        // that every launch keeps all gates and constants in registers (on
+        // the multi-morphology workloads the fuller uncapped packs have won)
+        for (int thr : {192, 256})
+            for (int nc2 : {2, 3}) {
+                Variant v = base;
+                v.sched = SIM_SCHED_DISPATCH;
+                v.threads = thr;
+                v.lds_limit = lds_for(s, kResident * thr);
+                v.nclass = nc2;
+                v.res_cap = true;
+                cand.push_back(v);
+            }
+        Variant v = base;
+        v.sched = SIM_SCHED_DISPATCH;
+        v.res_cap = true;
         cand.push_back(v);
     }
     double best = 1e30;

@@ -896,6 +896,8 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
         }
     }
     double *__restrict__ V = st.V;
+    const int lane = tid & (kWave - 1);
+    uint64_t spt = 0;  // lane t: this wave's crossings at step t (bit l: lane l's neuron)
     double *__restrict__ R = st.R;
     double *__restrict__ D = st.D;
     double *__restrict__ Eo = st.Eo;
@@ -1187,7 +1189,21 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                 if (more) membrane<T>(tp, af[i], m, h, x, ch, *(T *)&D[i], *(T *)&R[i]);
             }
         }
-        for (int k = tid; k < nn; k += NT) {
+        // detection: lane l of wave w watches neuron 64 w + l; a ballot
+        // gathers the step's threshold crossings of the wave's neurons into
+        // one mask, which lane t keeps (the masks are turned into per-neuron
+        // step masks once, at the end of the launch)
+        if (tid - lane < nn) {
+            bool cross = false;
+            if (tid < nn) {
+                const double vn = V[st.ND[2 * tid]];
+                cross = st.VO[tid] < cs.vth && vn >= cs.vth;
+                st.VO[tid] = vn;
+            }
+            const uint64_t m = __ballot(cross);
+            if (lane == t) spt = m;
+        }
+        for (int k = tid + NT; k < nn; k += NT) {  // packs of more neurons than threads
             const double vn = V[st.ND[2 * k]];
             if (st.VO[k] < cs.vth && vn >= cs.vth) st.SP[k] |= 1ull << t;
             st.VO[k] = vn;
@@ -1197,6 +1213,18 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     }
 
     // ---- write back -----------------------------------------------------------
+    // the wave's step masks, transposed by ballots: bit t of neuron l's mask
+    // is bit l of lane t's step mask
+    if (tid - lane < nn) {
+        const int nb = min(kWave, nn - (tid - lane));
+        uint64_t mine = 0;
+        for (int b = 0; b < nb; ++b) {
+            const uint64_t w = __ballot((spt >> b) & 1ull);
+            if (lane == b) mine = w;
+        }
+        if (lane < nb) st.SP[tid] = mine;
+    }
+    __syncthreads();
     for (int i = tid; i < n; i += NT) a.V[c0 + i] = V[i];
 #pragma unroll
     for (int j = 0; j < KR; ++j) {

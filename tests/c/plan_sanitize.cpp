@@ -15,7 +15,7 @@
 
 namespace mmh {
 hipError_t launch_setup(const SetupArgs &, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_epoch(const EpochArgs &, int, int, int, int, size_t, hipStream_t) {
+hipError_t launch_epoch(const EpochArgs &, int, int, int, int, size_t, bool, hipStream_t) {
     return hipErrorNotSupported;
 }
 hipError_t launch_fill_u64(uint64_t *, int64_t, uint64_t, hipStream_t) { return hipErrorNotSupported; }
