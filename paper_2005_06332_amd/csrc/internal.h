@@ -162,8 +162,10 @@ __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_
 // Bytes of the pack's tables staged in LDS next to the state: branch records,
 // synapse weights (T), level offsets, the forward order, child list, synapse
 // targets and run lengths. Must match the carve-up in the kernel.
-// The contraction solver adds its round offsets (nrnd + 1 ints; its items
-// stay in global memory); nrnd = 0 for the other solvers.
+// The contraction solver adds its round offsets (nrnd + 1 ints) and the
+// items staged in LDS (nst; the others stay in global memory), and stages no
+// branch records, forward order, child list or level offsets (nbr = nch =
+// nlev = 0); nrnd = 0 for the other solvers.
 template <typename T>
 __host__ __device__ inline int64_t pack_table_bytes(int64_t nbr, int64_t nch, int64_t nlev,
                                                     int64_t nsyn, int64_t ncomp = 0,

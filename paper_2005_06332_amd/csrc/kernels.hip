@@ -805,7 +805,9 @@ __device__ __forceinline__ void gates_update(const double v64, T &m, T &h, T &x,
 
 // The pack's tables, staged in LDS for the whole epoch: branch records (in
 // backward order), synapse weights, level offsets, the forward order (record
-// ids), child list, synapse targets and run lengths. The layout must match
+// ids), child list, synapse targets and run lengths; the contraction solver
+// stages none of the branch tables (kNoBranch), but its round offsets and
+// the items of its schedule's tail. The layout must match
 // pack_table_bytes().
 template <typename T>
 struct Tables {
@@ -818,17 +820,19 @@ struct Tables {
     uint64_t *cst;  // contraction items staged in LDS (the schedule's last ones)
 };
 
-template <typename T>
+template <typename T, bool kNoBranch>
 __device__ __forceinline__ Tables<T> carve_tables(char *smem, const PackDesc &pk) {
+    const int nbr = kNoBranch ? 0 : pk.nbr, nch = kNoBranch ? 0 : pk.nch;
+    const int nlev = kNoBranch ? 0 : pk.nbw + pk.nfw + 2;
     Tables<T> t;
     t.br = (Branch *)smem;
-    t.sw = (T *)(t.br + pk.nbr);
+    t.sw = (T *)(t.br + nbr);
     char *p = (char *)(t.sw + pk.nsyn);
     p = smem + (((p - smem) + 3) / 4) * 4;
     t.lvl = (int32_t *)p;
-    t.fw = (uint16_t *)(t.lvl + pk.nbw + pk.nfw + 2);
-    t.chl = t.fw + pk.nbr;
-    t.scomp = t.chl + pk.nch;
+    t.fw = (uint16_t *)(t.lvl + nlev);
+    t.chl = t.fw + nbr;
+    t.scomp = t.chl + nch;
     t.sseg = t.scomp + pk.nsyn;
     char *q = (char *)(t.sseg + pk.nsyn);
     t.crof = (int32_t *)(smem + (((q - smem) + 3) / 4) * 4);
@@ -866,22 +870,24 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const int n = pk.ncomp, ns = pk.nsyn, nn = pk.nneur;
     const int64_t c0 = pk.comp0, s0 = pk.syn0;
     const State<T> st = carve<T>(base, n, ns, nn);
-    const Tables<T> tb = carve_tables<T>(smem, pk);
+    const Tables<T> tb = carve_tables<T, kContract>(smem, pk);
 #ifdef MMH_PHASE_PROFILE
     uint64_t ph_t_ = threadIdx.x == 0 ? wall_clock64() : 0;
     uint64_t ph_acc_[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #endif
     {
-        const Branch *gbr = a.br + pk.br0;
-        const uint16_t *gfw = a.fw + pk.br0;
-        for (int k = tid; k < pk.nbr; k += NT) {
-            tb.br[k] = gbr[k];
-            tb.fw[k] = gfw[k];
+        if constexpr (!kContract) {
+            const Branch *gbr = a.br + pk.br0;
+            const uint16_t *gfw = a.fw + pk.br0;
+            for (int k = tid; k < pk.nbr; k += NT) {
+                tb.br[k] = gbr[k];
+                tb.fw[k] = gfw[k];
+            }
+            const uint16_t *gch = a.chl + pk.ch0;
+            for (int k = tid; k < pk.nch; k += NT) tb.chl[k] = gch[k];
+            const int32_t *glv = a.lvl + pk.lv0;
+            for (int k = tid; k < pk.nbw + pk.nfw + 2; k += NT) tb.lvl[k] = glv[k];
         }
-        const uint16_t *gch = a.chl + pk.ch0;
-        for (int k = tid; k < pk.nch; k += NT) tb.chl[k] = gch[k];
-        const int32_t *glv = a.lvl + pk.lv0;
-        for (int k = tid; k < pk.nbw + pk.nfw + 2; k += NT) tb.lvl[k] = glv[k];
         const T *gsw = (const T *)a.sw + s0;
         for (int k = tid; k < ns; k += NT) {
             tb.sw[k] = gsw[k];
@@ -910,8 +916,11 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const uint32_t *cnbp = a.cnb + c0;
     const T *niext = (const T *)a.niext;
     double *__restrict__ IX = st.IX;
-    const Branch *br = tb.br;
-    const uint16_t *chl = tb.chl;
+    // (the contraction solver's assembly reads a branch record and child
+    // list only for a compartment of more than two children: from global
+    // memory)
+    const Branch *br = kContract ? a.br + pk.br0 : tb.br;
+    const uint16_t *chl = kContract ? a.chl + pk.ch0 : tb.chl;
     const int32_t *lvl = tb.lvl;
 
     // Each constant is copied into a scalar register of its own: otherwise
@@ -1007,7 +1016,11 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
             if (i < n) assemble_cw<T>(i, rtp[j], rcw[j], rcdt[j], V, R, D, Eo, br, chl, IX, cs);
             __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (!kRes) {
+        if constexpr (kContract && !kRes) {
+#pragma unroll 2
+            for (int i = i0; i < n; i += NT)
+                assemble_cw<T>(i, topo[i], cnbp[i], cdtp[i], V, R, D, Eo, br, chl, IX, cs);
+        } else if constexpr (!kRes) {
 #pragma unroll 2
             for (int i = i0; i < n; i += NT)
                 assemble<T>(i, topo[i], cdtp[i], V, R, D, Eo, br, chl, IX, cs);

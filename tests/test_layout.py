@@ -40,13 +40,17 @@ def align(x, a):
 def table_bytes(info, tsize):
     """Tables as the kernel carves them: branch records (16 B), synapse
     weights, level offsets (4 B, 4-aligned), forward order and child list
-    (2 B each), synapse targets and run lengths (2 B each); then, for the
-    contraction solver, round offsets (4 B) and the items staged in LDS
-    (8 B, 8-aligned; the others stay in global memory); the whole rounded to
-    16 B."""
-    b = 16 * info["n_branches"] + tsize * info["n_syn"]
-    b = align(b, 4) + 4 * info["n_levels"]
-    b += 2 * info["n_branches"] + 2 * info["n_child_entries"] + 4 * info["n_syn"]
+    (2 B each), synapse targets and run lengths (2 B each); the contraction
+    solver stages no branch records, levels, forward order or child list,
+    but its round offsets (4 B) and the items staged in LDS (8 B, 8-aligned;
+    the others stay in global memory); the whole rounded to 16 B."""
+    # (the contraction solver, n_rounds > 0, stages no branch tables)
+    nbr, nlev, nch = info["n_branches"], info["n_levels"], info["n_child_entries"]
+    if info["n_rounds"] > 0:
+        nbr = nlev = nch = 0
+    b = 16 * nbr + tsize * info["n_syn"]
+    b = align(b, 4) + 4 * nlev
+    b += 2 * nbr + 2 * nch + 4 * info["n_syn"]
     if info["n_rounds"] > 0:
         b = align(b, 4) + 4 * (info["n_rounds"] + 1)
     if info["n_staged_items"] > 0:
