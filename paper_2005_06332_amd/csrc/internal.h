@@ -83,6 +83,21 @@ constexpr int kWave = 64;
 // step (it is then in the working slot, else it is the off-diagonal). Items
 // are stored by round; round r of a pack spans items rof[r] .. rof[r+1]-1.
 constexpr uint32_t kNoNb = 0xFFFF;
+// The same item as the epoch kernel reads it, in a pack of n compartments
+// whose state arrays have m = n + 1 entries: entry n is a spare compartment
+// that stands in for an absent neighbour (its off-diagonal entry is 0, so
+// the coupling it is read with is 0 and every update it takes is void).
+// Bits 0..14 k, 15..30 i1 (n1, or n when absent), 31..46 i2 (likewise),
+// 47..62 u1: where the coupling to n1 is read, as an index into the working
+// slot W followed by the off-diagonal (the two arrays are adjacent: u < m is
+// W[u], u >= m the off-diagonal entry u - m); bit 63 set when the coupling
+// to n2 is W[i2] (else the off-diagonal entry of i2).
+__host__ __device__ inline uint64_t make_citem(uint32_t k, uint32_t i1, uint32_t i2, uint32_t u1,
+                                               bool w2) {
+    return (uint64_t)(k & 0x7FFFu) | ((uint64_t)(i1 & 0xFFFFu) << 15) |
+           ((uint64_t)(i2 & 0xFFFFu) << 31) | ((uint64_t)(u1 & 0xFFFFu) << 47) |
+           (w2 ? (1ull << 63) : 0ull);
+}
 __host__ __device__ inline uint64_t make_item(uint32_t k, bool n1_parent, uint32_t n1,
                                               uint32_t n2, bool f1 = false, bool f2 = false) {
     return (uint64_t)(k & 0x7FFFu) | (n1_parent ? 0x8000ull : 0ull) | ((uint64_t)n1 << 16) |
@@ -150,9 +165,11 @@ struct EpochArgs {
 
 // Bytes of per-pack state for a pack of n compartments, s synapses and k
 // neurons in precision T (must match the carve-up in the kernel).
+// (The contraction solver's packs pass n + 1: their arrays end with a spare
+// compartment.)
 template <typename T>
 __host__ __device__ inline int64_t pack_state_bytes(int64_t n, int64_t s, int64_t k) {
-    int64_t b = 4 * 8 * n;                 // V, R, D, off-diagonal
+    int64_t b = 4 * 8 * n;                 // V, off-diagonal, R, D
     b += 8 * s + 8 * k + 8 * k;            // synapse masks, spike masks, V_det
     b += 8 * k + 8 * k;                    // external current, detector index
     b += ((int64_t)sizeof(T) * s + 15) / 16 * 16;  // synaptic conductances

@@ -287,10 +287,13 @@ template <typename T>
 __device__ __forceinline__ State<T> carve(char *base, int n, int s, int k) {
     State<T> p;
     double *dp = (double *)base;
+    // V, the off-diagonal, R, D: reads the blocked sweeps make a few
+    // elements before an array (R, D, off-diagonal) or past its end stay
+    // inside the pack's state or the slack after it
     p.V = dp;
-    p.R = dp + n;
-    p.D = dp + 2 * n;
-    p.Eo = dp + 3 * n;
+    p.Eo = dp + n;
+    p.R = dp + 2 * n;
+    p.D = dp + 3 * n;
     uint64_t *up = (uint64_t *)(dp + 4 * n);
     p.SM = up;
     p.SP = up + s;
@@ -581,56 +584,56 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // elimination: each neighbour's diagonal loses a^2/d_k and its right-hand
 // side a r_k/d_k; when both exist, n2 is linked to n1 with the coupling
 // -a1 a2/d_k. The V slot, free once the matrix is assembled, takes the
-// couplings made by these fills (W); a coupling no elimination has made yet
-// is still the off-diagonal, and the item says which of the two holds each
-// of k's couplings. What k's back substitution needs replaces what k no
-// longer needs: h = r_k/d_k into R[k], g1 = a1/d_k into W[k], g2 = a2/d_k
-// into D[k]. A round's eliminations are at least three apart in the current
-// tree, so each survivor is written by one lane at most.
+// couplings made by these fills (W, followed in memory by the off-diagonal:
+// a coupling no elimination has made yet is still the off-diagonal entry,
+// and the item gives the index of either, see make_citem). What k's back
+// substitution needs replaces what k no longer needs: h = r_k/d_k into
+// R[k], g1 = a1/d_k into W[k], g2 = a2/d_k into D[k]. A round's
+// eliminations are at least three apart in the current tree, so each
+// survivor is written by one lane at most.
 // k, n1 and n2 are distinct, so every value is read before anything is
-// written, and with no branches: the reads go out together (one LDS round
-// trip) rather than each waiting for the write before it, as they would if
-// the compiler had to assume the slots may alias. An absent neighbour
-// stands in for k: its reads are k's values and its writes put them back
-// unchanged, before k's own results are written.
+// written, with no branches and no selects: the reads go out together (one
+// LDS round trip) rather than each waiting for the write before it, as they
+// would if the compiler had to assume the slots may alias. An absent
+// neighbour is the pack's spare compartment, read with a coupling of 0: its
+// updates change nothing (they add -0 times a finite value), and a fill
+// made with it is never read (a compartment left without a parent is a
+// root from then on).
 __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
-                                              double *__restrict__ W,
-                                              const double *__restrict__ Eo, const uint64_t it) {
+                                              double *__restrict__ W, const int m,
+                                              const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
-    const bool up = (it >> 15) & 1u;
-    const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
-    const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
-    const int i1 = h1 ? (int)n1 : k, i2 = h2 ? (int)n2 : k;
-    const double *B1 = ((it >> 49) & 1u) ? W : Eo, *B2 = ((it >> 50) & 1u) ? W : Eo;
+    const int i1 = (int)(it >> 15) & 0xFFFF, i2 = (int)(it >> 31) & 0xFFFF;
+    const int u1 = (int)(it >> 47) & 0xFFFF;
+    const int u2 = (it >> 63) ? i2 : i2 + m;
     const double dk = D[k], rk = R[k];
-    const double w1 = B1[up ? k : i1], w2 = B2[i2];
+    const double a1 = W[u1], a2 = W[u2];
     const double d1 = D[i1], r1 = R[i1], d2 = D[i2], r2 = R[i2];
-    const double a1 = h1 ? w1 : 0.0, a2 = h2 ? w2 : 0.0;
     const double y = rcp_nr(dk);
     const double h = rk * y, g1 = a1 * y, g2 = a2 * y;
-    D[i1] = h1 ? __builtin_fma(-a1, g1, d1) : d1;
-    R[i1] = h1 ? __builtin_fma(-a1, h, r1) : r1;
-    D[i2] = h2 ? __builtin_fma(-a2, g2, d2) : d2;
-    R[i2] = h2 ? __builtin_fma(-a2, h, r2) : r2;
-    W[i2] = (h1 && h2) ? -(a1 * g2) : w2;
+    D[i1] = __builtin_fma(-a1, g1, d1);
+    R[i1] = __builtin_fma(-a1, h, r1);
+    D[i2] = __builtin_fma(-a2, g2, d2);
+    R[i2] = __builtin_fma(-a2, h, r2);
+    W[i2] = -(a1 * g2);
     R[k] = h;
     W[k] = g1;
     D[k] = g2;
 }
 
 // Back substitution of k, its neighbours at elimination time solved already
-// (their solutions in the V slot): x_k = h - g1 x_n1 - g2 x_n2, into V[k].
+// (their solutions in the V slot): x_k = h - g1 x_n1 - g2 x_n2, into V[k]
+// (an absent neighbour's g is 0).
 __device__ __forceinline__ void contract_subst(const double *__restrict__ R,
                                                const double *__restrict__ D,
                                                double *__restrict__ V, const uint64_t it) {
     const int k = (int)(it & 0x7FFFu);
-    const uint32_t n1 = (uint32_t)(it >> 16) & 0xFFFFu, n2 = (uint32_t)(it >> 32) & 0xFFFFu;
-    const bool h1 = n1 != kNoNb, h2 = n2 != kNoNb;
+    const int i1 = (int)(it >> 15) & 0xFFFF, i2 = (int)(it >> 31) & 0xFFFF;
     const double rk = R[k], g1 = V[k], g2 = D[k];
-    const double x1 = V[h1 ? (int)n1 : k], x2 = V[h2 ? (int)n2 : k];
+    const double x1 = V[i1], x2 = V[i2];
     double x = rk;
-    if (h1) x = __builtin_fma(-g1, x1, x);
-    if (h2) x = __builtin_fma(-g2, x2, x);
+    x = __builtin_fma(-g1, x1, x);
+    x = __builtin_fma(-g2, x2, x);
     V[k] = x;
 }
 
@@ -869,7 +872,9 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     const int slot = tid;
     const int n = pk.ncomp, ns = pk.nsyn, nn = pk.nneur;
     const int64_t c0 = pk.comp0, s0 = pk.syn0;
-    const State<T> st = carve<T>(base, n, ns, nn);
+    // (the contraction solver's arrays end with a spare compartment, n)
+    const int m = kContract ? n + 1 : n;
+    const State<T> st = carve<T>(base, m, ns, nn);
     const Tables<T> tb = carve_tables<T, kContract>(smem, pk);
 #ifdef MMH_PHASE_PROFILE
     uint64_t ph_t_ = threadIdx.x == 0 ? wall_clock64() : 0;
@@ -945,6 +950,12 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
     for (int i = tid; i < n; i += NT) {
         V[i] = a.V[c0 + i];
         Eo[i] = a.e[c0 + i];
+    }
+    if (kContract && tid == 0) {  // the spare compartment: a zero coupling, finite values
+        V[n] = 0.0;
+        Eo[n] = 0.0;
+        D[n] = 0.0;
+        R[n] = 0.0;
     }
 #pragma unroll
     for (int j = 0; j < KR; ++j) {
@@ -1055,9 +1066,9 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     // round's work and barrier
                     const int hi2 = (r + 1 < nr) ? rof[r + 2] : hi;
                     const uint64_t nxt = item(hi + tid, hi2);
-                    if (lo + tid < hi) contract_elim(D, R, V, Eo, cur);
+                    if (lo + tid < hi) contract_elim(D, R, V, m, cur);
                     for (int q2 = lo + tid + NT; q2 < hi; q2 += NT)
-                        contract_elim(D, R, V, Eo, cit[q2]);
+                        contract_elim(D, R, V, m, cit[q2]);
                     __syncthreads();
                     lo = hi;
                     hi = hi2;
@@ -1079,7 +1090,7 @@ __device__ __forceinline__ void run_pack(const EpochArgs &a, const PackDesc &pk,
                     for (int r = nw; r < nr; ++r) {
                         const int hi2 = (r + 1 < nr) ? rofw(r + 2) : hi;
                         const uint64_t nxt = tail_item(hi + tid);
-                        if (lo + tid < hi) contract_elim(D, R, V, Eo, cur);
+                        if (lo + tid < hi) contract_elim(D, R, V, m, cur);
                         wave_lds_sync();
                         lo = hi;
                         hi = hi2;

@@ -59,11 +59,14 @@ def table_bytes(info, tsize):
 
 
 def state_bytes(info, tsize):
-    """V, R, D and the off-diagonal (8 B per compartment each), synapse event
+    """V, the off-diagonal, R and D (8 B per compartment each; the
+    contraction solver's arrays have one spare entry more), synapse event
     masks (8 B), spike masks, detector voltages, external currents and
     detector indices (8 B per neuron each), synaptic conductances
     (16-aligned), 64 B of sweep slack."""
     n, s, k = info["n_comp"], info["n_syn"], info["n_neurons"]
+    if info["n_rounds"] > 0:
+        n += 1
     return 32 * n + 8 * s + 32 * k + align(tsize * s, 16) + 64
 
 
