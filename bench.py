@@ -210,7 +210,11 @@ def main():
     import torch
     from paper_2005_06332_amd import sim as S, costmodel
 
+    print(f"bench: generating {args.workload}", file=sys.stderr, flush=True)
     prob = make_workload(args.workload, args.neurons or None, args.precision)
+    print(f"bench: {args.workload} ready; creating the simulation "
+          f"({'fixed layout' if (args.no_autotune or args.lds_classes) else 'autotuning'})",
+          file=sys.stderr, flush=True)
     C = int(prob["comp_off"][-1])
     N = int(prob["n_comp"].shape[0])
     prec = int(prob["params"]["precision"])

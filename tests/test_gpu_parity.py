@@ -172,6 +172,25 @@ def test_single_compartment_and_tiny_neurons(S, orc):
     compare("mini with n=1 neurons", v, vr, s, sr)
 
 
+@pytest.mark.parametrize("threads", [64, 128])
+@pytest.mark.parametrize("solver", [0, 2])
+def test_packs_of_many_small_neurons_detect_every_spike(S, orc, solver, threads):
+    """Detection gathers a step's crossings with one ballot per wavefront of
+    64 neurons and transposes the epoch's masks at the end of the launch;
+    neurons beyond one per thread are handled one by one. Packs of 12-48
+    compartment neurons hold more neurons than a wavefront (and, with 64
+    threads, more than the workgroup's threads)."""
+    prob = W.mini(seed=41, n_neurons=400, n_steps=240, median=14)
+    kw = dict(solver=solver, threads=threads, lds_comps=3000)  # packs of 130-160 neurons
+    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, 240, 1, **kw)
+    compare(f"small neurons solver={solver} threads={threads}", v, vr, s, sr, tol(1, solver))
+    assert len(sr) > 0
+    with S.Simulation(prob, precision=1, **kw) as g:
+        most = max(g.pack_info(p)["n_neurons"] for p in range(g.pack_count()))
+    say(f"  most neurons in a pack: {most}")
+    assert most > 64 and (threads > 64 or most > threads)
+
+
 @pytest.mark.parametrize("solver", [0, 1, 2])
 def test_packing_and_launch_variants_are_bitwise_identical(S, solver):
     prob = W.mini(seed=29, n_steps=200, n_neurons=96)
