@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 
 import numpy as np
 
@@ -40,8 +41,11 @@ def _time(prob: dict, packing: int, steps: int, warmup: int, solver: int,
     finally:
         g.close()
     C = int(prob["comp_off"][-1])
-    return dict(ms_per_step=ms / steps, ns_per_update=ms * 1e6 / (C * steps),
-                compartments=C, epochs=epochs, launch=config)
+    out = dict(ms_per_step=ms / steps, ns_per_update=ms * 1e6 / (C * steps),
+               compartments=C, epochs=epochs, launch=config)
+    print(f"experiments: {prob['name']} packing={packing} "
+          f"{out['ns_per_update']:.5f} ns per update", file=sys.stderr, flush=True)
+    return out
 
 
 def imbalance(n_neurons: int = 10000, steps: int = 400, warmup: int = 40, seed: int = 7,
@@ -49,6 +53,7 @@ def imbalance(n_neurons: int = 10000, steps: int = 400, warmup: int = 40, seed: 
     """Mono vs multi-morphology under plain, count and learned packing."""
     mono = W.size_group(seed, n_neurons, mono=True)
     multi = W.size_group(seed, n_neurons, mono=False)
+    print("experiments: cost model", file=sys.stderr, flush=True)
     model = costmodel.load_or_train(solver=solver)
     runs = {
         "mono_plain": _time(mono, S.PACK_PLAIN, steps, warmup, solver),
@@ -95,7 +100,9 @@ def packing_bound(prob: dict, steps: int = 400, warmup: int = 40, reps: int = 3,
     the dispatch order that the packs' real times call for: what no
     prediction from neuron features can improve on. Runs alternate, reps
     times each."""
+    print("experiments: cost model", file=sys.stderr, flush=True)
     model = costmodel.load_or_train(solver=solver)
+    print("experiments: measured pack times", file=sys.stderr, flush=True)
     measured = measured_pack_costs(prob, steps, solver)
     runs = {"count": [], "learned (model)": [], "learned (measured pack times)": []}
     for _ in range(reps):
