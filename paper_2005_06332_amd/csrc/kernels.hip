@@ -191,15 +191,17 @@ __device__ __forceinline__ float fexprelr(float u) {
 }
 
 // x / c for the rate constants c. Float: q = RN(x RN(1/c)), then Markstein's
-// correction with the exact residual x - q c, carrying the sign of q (which
-// only matters for x = -0). For c = 10, 18, 20 and 80 this equals the
-// correctly rounded quotient for every float with 1e-30 <= |x| <= 1e30 and
-// for x = +-0 (checked exhaustively); the rate arguments v + const are 0 or
-// at least ulp(40) in magnitude. Double: the IEEE quotient.
+// correction with the exact residual x - q c. For c = 10, 18, 20 and 80 this
+// equals the correctly rounded quotient for every float with
+// 1e-30 <= |x| <= 1e30 (checked exhaustively), and for x = +0; x = -0 gives
+// +0 where the quotient is -0, which changes nothing, since the quotient only
+// enters exp and exprelr, and both give 1 at either zero. The rate arguments
+// v + const are 0 or at least ulp(40) in magnitude. Double: the IEEE
+// quotient.
 __device__ __forceinline__ float div_const(float x, float c, float rc) {
     const float q = x * rc;
     const float r = __builtin_fmaf(-q, c, x);
-    return __builtin_copysignf(__builtin_fmaf(r, rc, q), q);
+    return __builtin_fmaf(r, rc, q);
 }
 __device__ __forceinline__ double div_const(double x, double c, double) { return x / c; }
 
@@ -341,13 +343,14 @@ __device__ __forceinline__ double div_rn(double t, double d, double y) {
     return __builtin_fma(r, y, q);
 }
 
-// Reciprocal to about one ulp: hardware estimate and two Newton steps.
+// Reciprocal to about one ulp: the hardware estimate y (relative error e,
+// |e| < 2^-24), then one third-order step y (1 + e + e^2), which leaves a
+// relative error of order e^3 before the final rounding (three dependent
+// operations where two Newton steps take four).
 __device__ __forceinline__ double rcp_nr(double b) {
-    double y = __builtin_amdgcn_rcp(b);
-    double e = __builtin_fma(-b, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-b, y, 1.0);
-    return __builtin_fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(b);
+    const double e = __builtin_fma(-b, y, 1.0);
+    return __builtin_fma(y, __builtin_fma(e, e, e), y);
 }
 
 // Fast solver, between the sweeps: from (P, Q, S) of compartment i form

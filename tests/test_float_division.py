@@ -2,8 +2,9 @@
 20 and 80 with one multiplication by the rounded reciprocal and Markstein's
 correction (two fused multiply-adds) instead of a full division. This checks,
 on the CPU and for every float in the range the rate arguments can take,
-that the result equals the IEEE quotient bit for bit, which is what keeps the
-library's exact solver identical to the oracle."""
+that the result equals the IEEE quotient bit for bit (x = -0 may give +0:
+the quotient only enters exp and exprelr, which give 1 at either zero), which
+is what keeps the library's exact solver identical to the oracle."""
 import os
 import subprocess
 
