@@ -6,8 +6,10 @@
 // time stepping). While it does so the pack's voltages, off-diagonal,
 // synaptic conductances and the per-step matrix (diagonal D and right-hand
 // side R) stay in LDS (or, for packs too large for LDS, in a private slice
-// of global scratch); the gates and the time-invariant per-compartment
-// constants are read from global memory (mostly L2) every step.
+// of global scratch). With FP32 gating and the contraction solver the gates
+// and time-invariant constants of each thread's first kResident compartments
+// stay in registers for the epoch; the others' are read from global memory
+// (mostly L2) every step.
 //
 // Per step and pack, in the order of the paper's update (Section 2):
 //   A  synaptic delivery from the spike history, per-compartment conductance
@@ -15,14 +17,17 @@
 //      n), assembly of Eq. 2: D_i = C_i/dt + theta*sum G + g_i,
 //      R_i = C_i V_i/dt + J_i + (1-theta) * axial current
 //   C  backward sweep of Algorithm 1, one lane per branch, branches grouped
-//      by height so that every child is finished before its parent
-//   D  forward sweep of Algorithm 1, branches grouped by depth
+//      by height so that every child is finished before its parent (or the
+//      eliminations of a tree contraction, round by round)
+//   D  forward sweep of Algorithm 1, branches grouped by depth (or the
+//      contraction's back substitution, rounds in reverse)
 //   E  gates at V^{n+1} (exponential Euler); threshold-crossing detection
 // The exact solver performs every floating-point operation in the order of
 // Algorithm 1 as written (children of a node eliminated in descending index
 // order), with no contraction; the fast solver reassociates the elimination
-// into a division-free homogeneous form. In both, a neuron's arithmetic does
-// not depend on how neurons are packed or launched.
+// into a division-free homogeneous form, and the contraction solver performs
+// the same Gaussian elimination in another order. In all three, a neuron's
+// arithmetic does not depend on how neurons are packed or launched.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
