@@ -1652,14 +1652,22 @@ int lds_for(const sim_t *s, int comps) {
 // the fastest, then re-initialise. Candidates never change results: they only
 // move neurons between workgroups or memory spaces.
 
+constexpr int64_t kAutotuneShapesMaxComps = 50000000;
+
 void autotune(sim_t *s, Variant base) {
     // (pack_comps, LDS budget in compartments): small packs keep more
     // workgroups resident per CU, which hides the latency of the sweeps
     static const int kShapes[][2] = {{300, 420},  {400, 550},   {500, 680},  {600, 800},
                                      {800, 1100}, {1000, 1300}, {1400, 1800}};
+    // Every trial lays the network out again on the host, which takes seconds
+    // at 1e8 compartments: there the pack-shape sweep (whose winner has been
+    // the default shape on every multi-morphology workload measured) is left
+    // out and only the class structure is tried.
+    const bool large = s->C > kAutotuneShapesMaxComps;
     std::vector<Variant> cand;
     for (int thr : {128, 256, 320})
         for (const auto &sh : kShapes) {
+            if (large) break;
             Variant v = base;
             v.threads = thr;
             v.pack_comps = sh[0];
