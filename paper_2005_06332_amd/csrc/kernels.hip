@@ -783,7 +783,7 @@ __device__ __forceinline__ void assemble_cw(const int i, const uint32_t tp, cons
     const double v = V[i];
     const T gmem = *(const T *)&D[i];
     const T jm = *(const T *)&R[i];
-    const T ix = *(const T *)&IX[pi];
+    const T ix = *(const T *)&IX[root ? pi : 0];  // (IX holds one entry per neuron)
     const double ei = Eo[i], vp = V[pi];
     const double e1 = Eo[c1], v1 = V[c1], e2 = Eo[c2], v2 = V[c2];
     const T J = jm + (root ? ix : T(0));
