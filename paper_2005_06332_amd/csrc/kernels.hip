@@ -603,10 +603,11 @@ __device__ __forceinline__ void sweep_fwd_blk(double *__restrict__ V, const doub
 // written, with no branches and no selects: the reads go out together (one
 // LDS round trip) rather than each waiting for the write before it, as they
 // would if the compiler had to assume the slots may alias. An absent
-// neighbour is the pack's spare compartment, read with a coupling of 0: its
-// updates change nothing (they add -0 times a finite value), and a fill
-// made with it is never read (a compartment left without a parent is a
-// root from then on).
+// neighbour is the pack's spare compartment, read with a coupling of 0: the
+// updates meant for it land in the spare's own slots, which stay finite and
+// are only ever read multiplied by a zero coupling, and a fill made with it
+// is never read (a compartment left without a parent is a root from then
+// on).
 __device__ __forceinline__ void contract_elim(double *__restrict__ D, double *__restrict__ R,
                                               double *__restrict__ W, const int m,
                                               const uint64_t it) {
@@ -759,10 +760,10 @@ __device__ __forceinline__ void assemble(const int i, const uint32_t tp, const d
 
 // Phase B with the compartment's children word (chw, see make_children):
 // the same operations in the same order as assemble(), but every operand is
-// read at once, with no dependent read of a branch record or child list
-// (an absent parent or child reads the compartment's own slots and its term
-// is not applied). A compartment with more than two children takes
-// assemble()'s path.
+// read at once, with no dependent read of a branch record or child list (an
+// absent child reads the compartment's own slots, a root reads the slot its
+// topology word names in place of a parent's, and neither term is applied).
+// A compartment with more than two children takes assemble()'s path.
 template <typename T>
 __device__ __forceinline__ void assemble_cw(const int i, const uint32_t tp, const uint32_t chw,
                                             const double cdt, const double *__restrict__ V,
