@@ -251,6 +251,21 @@ int sim_workgroup_packs(const sim_t *sim, int32_t cls, int32_t wg, int32_t *pack
  * queries *n_rounds. */
 int sim_contraction_schedule(const sim_t *sim, int32_t neuron, int32_t *items, int64_t cap,
                              int32_t *round_off, int64_t cap_rounds, int32_t *n_rounds);
+/* The contraction items of pack `pack` as the epoch kernel reads them, in
+ * execution order (round by round), for a simulation laid out with
+ * sim_plan_create under SIM_SOLVE_CONTRACT (SIM_ESTATE otherwise). One
+ * 64-bit item per compartment, pack-local indices: bits 0..14 the
+ * eliminated compartment k; bits 15..30 and 31..46 its two neighbours at
+ * elimination time, where the pack's spare compartment n_comp stands for an
+ * absent one; bits 47..62 where the coupling to the first neighbour is read,
+ * as an index into the working couplings (below n_comp + 1) followed by the
+ * off-diagonal (index - n_comp - 1); bit 63 set when the coupling to the
+ * second neighbour is a working coupling (else its off-diagonal entry).
+ * *n receives the count; items == NULL only queries it.
+ * Host-only introspection of this library's layout (no passage of the
+ * paper defines it). */
+int sim_pack_contraction_items(const sim_t *sim, int32_t pack, uint64_t *items, int64_t cap,
+                               int64_t *n);
 
 /* Advance by n_steps (>= 0) time steps; returns when the work is complete
  * on the device, with the steps' spikes recorded (see sim_spikes).

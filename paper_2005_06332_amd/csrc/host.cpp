@@ -1898,7 +1898,12 @@ int sim_plan_create(const sim_params_t *params, const sim_morphology_t *morph,
         s->n_cu = n_cu;
         compute_cost(s);
         build_layout(s, variant_from(s, params));
-        s->hl = sim_t::HostLayout{};
+        {
+            // a planned layout keeps its contraction items for introspection
+            std::vector<uint64_t> cit = std::move(s->hl.cit);
+            s->hl = sim_t::HostLayout{};
+            s->hl.cit = std::move(cit);
+        }
         s->config = describe(s);
         *out = s;
         return SIM_OK;
@@ -1996,6 +2001,19 @@ int sim_contraction_schedule(const sim_t *s, int32_t neuron, int32_t *items, int
     }
     const int32_t *ro = s->croff.data() + s->croff0[neuron];
     for (int32_t r = 0; r <= nr; ++r) round_off[r] = ro[r];
+    return SIM_OK;
+}
+
+int sim_pack_contraction_items(const sim_t *s, int32_t pack, uint64_t *items, int64_t cap,
+                               int64_t *n) {
+    if (!s || pack < 0 || pack >= (int32_t)s->packs.size() || !n) return SIM_EINVAL;
+    if (s->solver != SIM_SOLVE_CONTRACT || !s->planned_only) return SIM_ESTATE;
+    const PackDesc &d = s->packs[pack];
+    *n = d.ncomp;
+    if (!items) return SIM_OK;
+    if (cap < d.ncomp) return SIM_EINVAL;
+    if ((int64_t)d.it0 + d.ncomp > (int64_t)s->hl.cit.size()) return SIM_ESTATE;
+    std::copy(s->hl.cit.begin() + d.it0, s->hl.cit.begin() + d.it0 + d.ncomp, items);
     return SIM_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTS = (
     "sim_mlp_forward", "sim_mlp_loss_grad", "sim_mlp_train",
     "sim_plan_create", "sim_pack_count", "sim_pack_info", "sim_pack_neurons",
     "sim_class_launch", "sim_workgroup_packs", "sim_contraction_schedule",
-    "sim_step_noalloc",
+    "sim_pack_contraction_items", "sim_step_noalloc",
 )
 
 
@@ -150,6 +150,8 @@ def lib():
                                           C.POINTER(C.c_int32)]
         L.sim_contraction_schedule.argtypes = [P, C.c_int32, P, C.c_int64, P, C.c_int64,
                                                C.POINTER(C.c_int32)]
+        L.sim_pack_contraction_items.argtypes = [P, C.c_int32, P, C.c_int64,
+                                                 C.POINTER(C.c_int64)]
         L.sim_step_noalloc.argtypes = [P, C.c_int64, P, C.c_int64, C.POINTER(C.c_int64)]
         L.sim_step_noalloc.restype = C.c_int
         L.sim_mlp_nparams.restype = C.c_int64
@@ -162,7 +164,7 @@ def lib():
                   "sim_kernel_time", "sim_class_time", "sim_mlp_init", "sim_mlp_forward",
                   "sim_mlp_loss_grad", "sim_mlp_train", "sim_plan_create", "sim_pack_info",
                   "sim_pack_neurons", "sim_class_launch", "sim_workgroup_packs",
-                  "sim_contraction_schedule"):
+                  "sim_contraction_schedule", "sim_pack_contraction_items"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -367,6 +369,17 @@ class Simulation:
         _check(lib().sim_contraction_schedule(self._h, int(neuron), _p(items), items.size,
                                               _p(ro), ro.size, C.byref(nr)), self._h)
         return items, ro
+
+    def pack_contraction_items(self, pack: int) -> np.ndarray:
+        """The pack's contraction items as the epoch kernel reads them (a
+        planned layout under the contraction solver; see
+        sim_pack_contraction_items)."""
+        n = C.c_int64(0)
+        _check(lib().sim_pack_contraction_items(self._h, int(pack), None, 0, C.byref(n)), self._h)
+        out = np.empty(n.value, np.uint64)
+        _check(lib().sim_pack_contraction_items(self._h, int(pack), _p(out), out.size,
+                                                C.byref(n)), self._h)
+        return out
 
     def set_kernel_timing(self, on: bool) -> None:
         _check(lib().sim_set_kernel_timing(self._h, int(on)), self._h)

@@ -108,6 +108,14 @@ int main(int argc, char **argv) {
                         }
                     }
                     if (solver == 2)
+                        for (int32_t pk = 0; pk < sim_pack_count(s); ++pk) {
+                            int64_t n = 0;
+                            if (sim_pack_contraction_items(s, pk, nullptr, 0, &n) != SIM_OK) return 1;
+                            std::vector<uint64_t> items(n > 0 ? n : 1);
+                            if (sim_pack_contraction_items(s, pk, items.data(), n, &n) != SIM_OK)
+                                return 1;
+                        }
+                    if (solver == 2)
                         for (int32_t j = 0; j < M.n_neurons; ++j) {
                             int32_t nr = 0;
                             sim_contraction_schedule(s, j, nullptr, 0, nullptr, 0, &nr);

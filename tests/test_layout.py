@@ -12,7 +12,8 @@ as sim_create would for a given LDS size and CU count, without a device.
 - the contraction solver's elimination schedule eliminates every compartment
   once, each round's compartments are at distance >= 3 in the contracted
   tree and have degree <= 2, and executing it solves the tree system (checked
-  against a dense solve).
+  against a dense solve); so do the pack-level items in the epoch kernel's
+  own encoding.
 """
 import itertools
 
@@ -288,6 +289,80 @@ def test_contraction_schedule_is_a_valid_elimination(S, which):
             x = execute_schedule(items, ro, p, e, d, rhs)
             ref = np.linalg.solve(A, rhs)
             assert np.max(np.abs(x - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def execute_pack_items(items, n, e, d, r):
+    """The epoch kernel's elimination and back substitution over a pack's
+    items as it reads them (sim_pack_contraction_items), in numpy: arrays
+    of n + 1 entries (the last is the spare compartment, off-diagonal 0),
+    couplings read from the working slot W followed by the off-diagonal.
+    The items run one after another, the back substitution in reverse: the
+    kernel's rounds only group items that touch disjoint slots, so the
+    result is the same."""
+    m = n + 1
+    D, R = np.append(d, 0.0), np.append(r, 0.0)
+    WE = np.concatenate([np.zeros(m), np.append(e, 0.0)])  # W, then the off-diagonal
+    its = [int(x) for x in items]
+    for it in its:
+        k, i1, i2 = it & 0x7FFF, (it >> 15) & 0xFFFF, (it >> 31) & 0xFFFF
+        u1 = (it >> 47) & 0xFFFF
+        u2 = i2 if it >> 63 else i2 + m
+        a1, a2 = WE[u1], WE[u2]
+        dk, rk = D[k], R[k]
+        d1, r1, d2, r2 = D[i1], R[i1], D[i2], R[i2]
+        y = 1.0 / dk
+        h, g1, g2 = rk * y, a1 * y, a2 * y
+        D[i1], R[i1] = d1 - a1 * g1, r1 - a1 * h
+        D[i2], R[i2] = d2 - a2 * g2, r2 - a2 * h
+        WE[i2] = -(a1 * g2)
+        R[k], WE[k], D[k] = h, g1, g2
+    V = WE[:m].copy()  # the back substitution writes x over the W slot
+    for it in reversed(its):
+        k, i1, i2 = it & 0x7FFF, (it >> 15) & 0xFFFF, (it >> 31) & 0xFFFF
+        V[k] = R[k] - V[k] * V[i1] - D[k] * V[i2]
+    return V[:n]
+
+
+@pytest.mark.parametrize("which", ["mini", "cfg1", "star", "cfg3"])
+def test_pack_items_as_the_kernel_reads_them_solve_the_pack(S, which):
+    """Every item of every pack, in the kernel's encoding (absent neighbours
+    as the spare compartment, the first coupling by one index into the
+    working slot and the off-diagonal), eliminates its compartment once,
+    and executing them solves each pack's tree systems (a dense solve of the
+    pack's block-diagonal matrix)."""
+    prob = {"mini": lambda: W.mini(), "cfg1": W.config1, "star": W.star_network,
+            "cfg3": lambda: W.subset(W.make(3), np.arange(200))}[which]()
+    rng = np.random.default_rng(17)
+    off = prob["comp_off"]
+    with plan(S, prob, solver=2) as g:
+        for pk in range(g.pack_count()):
+            items = g.pack_contraction_items(pk)
+            n = g.pack_info(pk)["n_comp"]
+            assert items.shape == (n,)
+            k = (items & np.uint64(0x7FFF)).astype(np.int64)
+            assert sorted(k.tolist()) == list(range(n))
+            # the pack's tree: its neurons in pack order, compartments in order
+            p = np.empty(n, np.int64)
+            base = 0
+            for j in g.pack_neurons(pk):
+                pj = prob["parent"][off[j]:off[j + 1]].astype(np.int64)
+                p[base:base + pj.shape[0]] = np.where(pj >= 0, pj + base, -1)
+                base += pj.shape[0]
+            assert base == n
+            child = np.flatnonzero(p >= 0)
+            e = np.zeros(n)
+            e[child] = -rng.uniform(0.05, 1.0, child.shape[0])
+            dd = np.zeros(n)
+            np.add.at(dd, child, -e[child])
+            np.add.at(dd, p[child], -e[child])
+            d = dd + rng.uniform(0.2, 1.5, n)
+            rhs = rng.normal(size=n)
+            A = np.diag(d)
+            A[child, p[child]] = e[child]
+            A[p[child], child] = e[child]
+            x = execute_pack_items(items, n, e, d, rhs)
+            ref = np.linalg.solve(A, rhs)
+            assert np.max(np.abs(x - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref))), pk
 
 
 @pytest.mark.parametrize("which", ["cfg3 subset", "cfg1", "star"])
