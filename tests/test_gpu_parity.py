@@ -266,18 +266,26 @@ def test_full_size_multimorphology_matches_oracle(S, orc):
     (2, 0, 0, 80), (2, 0, 1, 80), (2, 0, 2, 80), (4, 1, 1, 80), (4, 1, 0, 80), (4, 1, 2, 80),
     (5, 1, 1, 40), (5, 1, 2, 40),
 ])
-def test_other_full_size_configs_match_oracle(S, orc, cfg, precision, solver, steps):
+def test_other_full_size_configs_match_oracle(S, full_workload, oracle_full, cfg, precision,
+                                              solver, steps):
     """The other full-size workloads against the oracle in the same precision,
     with count packing (autotuned as bench.py runs them, except cfg5): cfg2 (8192
     identical neurons of 1000 compartments, all-FP64), cfg4 (32768
     multi-morphology neurons, FP32 gating) and cfg5 (1e5 neurons, 1.13e8
     compartments, delays 40..200 steps; one epoch), every voltage and every
-    spike."""
-    prob = W.make(cfg)
+    spike. The oracle's run of each (workload, steps, precision) is shared by
+    the solvers."""
+    prob = full_workload(cfg)
+    say(f"case full cfg{cfg} N={prob['n_comp'].shape[0]} steps={steps} prec={precision} "
+        f"solver={solver}")
+    vr, sr = oracle_full(cfg, steps, precision)
     # cfg5 keeps the default layout (two size classes, its largest neurons in
     # global scratch): the autotuner's trial layouts of 1e5 neurons take long
-    (v, s, _, _), (vr, sr, _, _) = run_pair(S, orc, prob, steps, precision, solver=solver,
-                                            autotune=(cfg != 5))
+    with S.Simulation(prob, precision=precision, solver=solver, autotune=(cfg != 5)) as g:
+        say("  config:", g.config)
+        g.step(steps)
+        assert g.step_count == steps
+        v, s = g.voltages(), g.spikes()
     compare(f"full cfg{cfg} prec={precision} solver={solver}", v, vr, s, sr,
             tol(precision, solver))
 

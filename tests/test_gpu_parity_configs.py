@@ -64,24 +64,24 @@ def compare(tag, v_gpu, v_ref, s_gpu, s_ref, tol_mv):
     assert s_gpu.shape == s_ref.shape and np.array_equal(s_gpu, s_ref), tag
 
 
-def full_pair(S, orc, prob, steps, precision, **kw):
+def full_pair(S, full_workload, oracle_full, cfg, steps, precision, **kw):
+    """The GPU run of a full-size workload and the oracle's run of it (shared
+    by every variant of one workload, step count and precision)."""
+    prob = full_workload(cfg)
     say(f"case {prob['name']} N={prob['n_comp'].shape[0]} C={int(prob['comp_off'][-1])} "
         f"steps={steps} prec={precision} {sorted(k for k in kw if k != 'cost_model')}")
     with S.Simulation(prob, precision=precision, **kw) as g:
         say("  config:", g.config)
         g.step(steps)
         v, s = g.voltages(), g.spikes()
-    ref = orc.Sim(prob, max_steps=steps, precision=precision)
-    ref.step(steps)
-    vr, sr = ref.voltages(), ref.spikes()
-    ref.close()
+    vr, sr = oracle_full(cfg, steps, precision)
     return v, s, vr, sr
 
 
 @pytest.mark.parametrize("solver", [0, 1, 2])
-def test_cfg2_fp32_gating_full_size(S, orc, solver):
-    prob = W.make(2)
-    v, s, vr, sr = full_pair(S, orc, prob, 80, 1, solver=solver, autotune=(solver != 0))
+def test_cfg2_fp32_gating_full_size(S, full_workload, oracle_full, solver):
+    v, s, vr, sr = full_pair(S, full_workload, oracle_full, 2, 80, 1, solver=solver,
+                             autotune=(solver != 0))
     compare(f"full cfg2 FP32 gating solver={solver}", v, vr, s, sr, tol(1, solver))
 
 
@@ -92,10 +92,9 @@ def cost_model(S):
 
 
 @pytest.mark.parametrize("solver", [0, 1, 2])
-def test_cfg4_learned_packing_full_size(S, orc, cost_model, solver):
-    prob = W.make(4)
-    v, s, vr, sr = full_pair(S, orc, prob, 80, 1, solver=solver, packing=S.PACK_LEARNED,
-                             cost_model=cost_model)
+def test_cfg4_learned_packing_full_size(S, full_workload, oracle_full, cost_model, solver):
+    v, s, vr, sr = full_pair(S, full_workload, oracle_full, 4, 80, 1, solver=solver,
+                             packing=S.PACK_LEARNED, cost_model=cost_model)
     compare(f"full cfg4 learned packing solver={solver}", v, vr, s, sr, tol(1, solver))
     assert len(sr) > 1000
 
@@ -194,25 +193,26 @@ def fp32_error_report(S, orc, name, prob, steps=4000, **kw):
     return worst, cmin, gmin
 
 
-def test_fp32_error_cfg2_full_length(S, orc):
-    fp32_error_report(S, orc, "cfg2", W.make(2, precision=1), autotune=True)
+def test_fp32_error_cfg2_full_length(S, orc, full_workload):
+    fp32_error_report(S, orc, "cfg2", full_workload(2, precision=1), autotune=True)
 
 
-def test_fp32_error_cfg4_full_length(S, orc, cost_model):
-    fp32_error_report(S, orc, "cfg4", W.make(4), packing=S.PACK_LEARNED, cost_model=cost_model)
+def test_fp32_error_cfg4_full_length(S, orc, full_workload, cost_model):
+    fp32_error_report(S, orc, "cfg4", full_workload(4), packing=S.PACK_LEARNED,
+                      cost_model=cost_model)
 
 
-def test_fp32_error_cfg5_full_length(S, orc):
+def test_fp32_error_cfg5_full_length(S, orc, full_workload):
     """cfg5 over 4000 steps (every delay class 40..200 steps delivers many
     times), default layout with its largest neurons in global scratch."""
-    fp32_error_report(S, orc, "cfg5", W.make(5))
+    fp32_error_report(S, orc, "cfg5", full_workload(5))
 
 
-def test_cfg5_exact_replay_delivers_every_delay(S, orc):
+def test_cfg5_exact_replay_delivers_every_delay(S, orc, full_workload):
     """cfg5 with the exact solver over 480 steps (12 epochs, so delays of up to
     200 steps deliver at full size), replayed per neuron: bitwise in
     practice, 1e-9 mV stated."""
-    prob = W.make(5)
+    prob = full_workload(5)
     steps = 480
     N = prob["n_comp"].shape[0]
     targets = replay_targets(prob)
