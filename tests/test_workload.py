@@ -142,3 +142,32 @@ def test_star_network_has_high_fanout_somata():
         p = prob["parent"][off[j]:off[j + 1]]
         assert p[0] == -1 and np.all(p[1:] < np.arange(1, p.shape[0]))
         assert int(np.sum(p == 0)) in (64, 5)
+
+
+def test_shared_workloads_hand_out_isolated_read_only_problems(orc):
+    """The GPU suite's session caches: one generation per workload, equal to a
+    fresh one; every call a new dict whose params and channels are its own; the
+    arrays read-only; and the shared oracle run equal to a direct one, made
+    once per (workload, steps, precision)."""
+    from conftest import SharedOracleRuns, SharedWorkloads
+    fw = SharedWorkloads()
+    a, b = fw(1), fw(1)
+    fresh = W.make(1)
+    assert a is not b and a["params"] is not b["params"] and a["channels"] is not b["channels"]
+    for k, v in fresh.items():
+        if isinstance(v, np.ndarray):
+            assert a[k] is b[k] and np.array_equal(a[k], v) and not a[k].flags.writeable
+            with pytest.raises(ValueError):
+                a[k][...] = 0
+        else:
+            assert a[k] == v
+    a["params"]["theta"] = 1.0
+    assert fw(1)["params"]["theta"] == fresh["params"]["theta"]
+    runs = SharedOracleRuns(orc, fw)
+    v1, s1 = runs(1, 40, 1)
+    v2, s2 = runs(1, 40, 1)
+    assert v1 is v2 and s1 is s2 and not v1.flags.writeable
+    ref = orc.Sim(fresh, max_steps=40, precision=1)
+    ref.step(40)
+    assert np.array_equal(v1, ref.voltages()) and np.array_equal(s1, ref.spikes())
+    ref.close()
