@@ -141,9 +141,12 @@ def copy_bandwidth(stream) -> float:
     return 2.0 * 4 * n / (best / 1e3) / 1e9
 
 
-def cpu_baseline(prob: dict, target_s: float = 15.0):
+def cpu_baseline(prob: dict, target_s: float = 20.0):
     """The oracle on a bounded sample of the same workload: the first neurons
-    of the network (with the synapses among them) for a short run."""
+    of the network (with the synapses among them) for a short run, sized for
+    about target_s seconds. The short probe that sizes it includes the
+    oracle's set-up, so on many cores it underestimates the rate (by 42% on
+    16 threads): a 20 s target keeps the run between 10 and 30 s either way."""
     from oracle import oracle as O
     O.build(force=False)
     n_all = prob["n_comp"].shape[0]
