@@ -95,28 +95,29 @@ def _dfs_order(bpar, children):
 def _build_neuron(bpar, children, lens, d0, d1):
     """Compartment arrays of one neuron: soma at 0, then branches in DFS order,
     each branch contiguous from its base (proximal) to its tip (distal).
-    lens/d0/d1 are indexed by branch id (creation order)."""
-    order = _dfs_order(bpar, children)
-    n = 1 + int(sum(lens))
+    lens/d0/d1 are indexed by branch id (creation order); every branch has at
+    least one compartment. A branch's diameter tapers linearly from d0 at its
+    base to d1 at its tip, sampled at the compartment midpoints."""
+    order = np.asarray(_dfs_order(bpar, children), np.int64)
+    lens = np.asarray(lens, np.int64)
+    L = lens[order]                                   # branch lengths, DFS order
+    n = 1 + int(L.sum())
+    first = np.empty(lens.shape[0], np.int64)         # first compartment, by branch id
+    first[order] = 1 + np.concatenate(([0], np.cumsum(L)[:-1]))
+    tip = first + lens - 1
+    bp = np.asarray(bpar, np.int64)
+    base_parent = np.where(bp < 0, 0, tip[np.maximum(bp, 0)])
+    br = np.repeat(order, L)                          # branch of compartments 1..n-1
+    local = np.arange(1, n, dtype=np.int64) - first[br]
     parent = np.empty(n, np.int32)
-    length = np.empty(n, np.float64)
-    diam = np.empty(n, np.float64)
     parent[0] = -1
+    parent[1:] = np.where(local == 0, base_parent[br], np.arange(n - 1, dtype=np.int64))
+    length = np.full(n, DEND_L_UM, np.float64)
     length[0] = SOMA_L_UM
+    diam = np.empty(n, np.float64)
     diam[0] = SOMA_D_UM
-    tip = {}
-    pos = 1
-    for b in order:
-        L = int(lens[b])
-        base_parent = 0 if bpar[b] < 0 else tip[bpar[b]]
-        idx = np.arange(pos, pos + L)
-        parent[pos] = base_parent
-        parent[pos + 1:pos + L] = idx[:-1]
-        length[pos:pos + L] = DEND_L_UM
-        frac = (np.arange(L) + 0.5) / L
-        diam[pos:pos + L] = d0[b] + (d1[b] - d0[b]) * frac
-        tip[b] = pos + L - 1
-        pos += L
+    frac = (local + 0.5) / lens[br]
+    diam[1:] = d0[br] + (d1[br] - d0[br]) * frac
     return parent, length, diam
 
 
